@@ -1,0 +1,70 @@
+"""Global diagnostics: energies, cross-helicity, current, divergence, invariants (paper Sec.
+4.4: mean energies, <|J|^2>, dissipation; eq. LB_B_div) and shell energy spectra (Sec. 4.4).
+
+Reduction slots, in order:
+  0 E_kin = 1/2 <|u|^2>            1 E_mag = 1/2 <|B - b0|^2>      2 H_c = <u . (B - b0)>
+  3 <|J|^2>                        4 max |div B|                   5 rms div B
+  6 max |u|                        7 rms (rho - 1)                 8 nodes with a non-finite value
+  9 sum rho                        10..12 sum rho u                13..15 sum B
+div B is the moment estimate -(w_B / C^2) Tr Lambda.
+
+Spectrum of a vector field v on an n^3 grid: E(s) = 1/2 sum_{round(|k|) = s} |v_hat(k)|^2 with
+v_hat = DFT(v) / n^3 and k the signed integer wavevector; by Parseval sum_s E(s) = 1/2 <|v|^2>.
+"""
+
+import math
+
+import numpy as np
+import torch
+
+from . import scheme
+
+NRED = 16
+
+
+def reductions(st, p):
+    rho, U, B, J, divb = scheme.fields(st, p)
+    b0 = torch.tensor(p.b0, dtype=torch.float64).view(3, 1, 1, 1)
+    bb = B - b0
+    bad = ~(torch.isfinite(st.f).all(0) & torch.isfinite(st.g).all(0).all(0))
+    out = torch.zeros(NRED, dtype=torch.float64)
+    out[0] = 0.5 * (U * U).sum(0).mean()
+    out[1] = 0.5 * (bb * bb).sum(0).mean()
+    out[2] = (U * bb).sum(0).mean()
+    out[3] = (J * J).sum(0).mean()
+    out[4] = divb.abs().max()
+    out[5] = (divb * divb).mean().sqrt()
+    out[6] = (U * U).sum(0).sqrt().max()
+    out[7] = ((rho - 1.0) ** 2).mean().sqrt()
+    out[8] = bad.sum()
+    out[9] = rho.sum()
+    out[10:13] = (rho.unsqueeze(0) * U).sum((1, 2, 3))
+    out[13:16] = B.sum((1, 2, 3))
+    return out
+
+
+def shell_index(shape):
+    """round(|k|) for every DFT index of a (nz, ny, nx) grid (signed integer k per axis)."""
+    nz, ny, nx = shape
+    kz = np.fft.fftfreq(nz, 1.0 / nz)
+    ky = np.fft.fftfreq(ny, 1.0 / ny)
+    kx = np.fft.fftfreq(nx, 1.0 / nx)
+    kk = np.sqrt(kz[:, None, None] ** 2 + ky[None, :, None] ** 2 + kx[None, None, :] ** 2)
+    return np.floor(kk + 0.5).astype(np.int64)
+
+
+def spectrum(v, nshells):
+    """Shell energy spectrum of a (3, nz, ny, nx) real field; shells 0..nshells-1."""
+    arr = v.detach().cpu().numpy() if torch.is_tensor(v) else np.asarray(v)
+    n = arr[0].size
+    e = np.zeros(nshells)
+    s = shell_index(arr.shape[1:])
+    for b in range(3):
+        vh = np.fft.fftn(arr[b]) / n
+        e += np.bincount(s.ravel(), weights=0.5 * np.abs(vh.ravel()) ** 2, minlength=nshells)[:nshells]
+    return e
+
+
+def max_shell(shape):
+    nz, ny, nx = shape
+    return int(math.floor(math.sqrt((nz // 2) ** 2 + (ny // 2) ** 2 + (nx // 2) ** 2) + 0.5)) + 1

@@ -1,0 +1,211 @@
+"""Pins of the whole oracle step against the exact Hall-MHD wave (paper Sec. 4.1), second-order
+convergence under diffusive scaling (Sec. 4.3), exact invariants, symmetry, the initial state,
+forcing closed forms, and the weak-compressibility level of the validation runs (Sec. 4.2).
+"""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import synthetic
+from oracle import analytic, diagnostics, scheme
+from oracle.lattice import C, C2, CS2, XI
+
+TOL_WAVE = {"stencil": 0.01, "moment": 0.05}
+
+
+def _wave_run(N, steps, amp, b0, d_i, nu=0.01, branch=+1, jmode="stencil", nx=1, ny=1,
+              route="closed"):
+    p = scheme.Params(nx, ny, N, nu, nu, d_i, (0.0, 0.0, b0), jmode, route)
+    be = analytic.beta(d_i, 2 * math.pi / N, branch)
+    uf = synthetic.wave_field(amp)
+    u, gu = synthetic.evaluate(uf, (nx, ny, N))
+    b, gb = synthetic.evaluate(synthetic.scaled(uf, be), (nx, ny, N))
+    st = scheme.step(scheme.init_state(p, u, b, gu, gb), p, steps)
+    return p, st
+
+
+def _wave_error(N, steps, amp, b0, d_i, **kw):
+    p, st = _wave_run(N, steps, amp, b0, d_i, **kw)
+    _, U, B, _, _ = scheme.fields(st, p)
+    ue, be = analytic.wave(N, steps, amp, b0, p.nu, d_i, kw.get("branch", +1))
+    eu = torch.linalg.norm(U[:, :, 0, 0] - ue) / torch.linalg.norm(ue)
+    bf = be.clone()
+    bf[2] -= b0
+    eb = torch.linalg.norm(B[:, :, 0, 0] - be) / torch.linalg.norm(bf)
+    return float(eu), float(eb)
+
+
+@pytest.mark.parametrize("jmode", ["stencil", "moment"])
+@pytest.mark.parametrize("branch", [+1, -1])
+def test_exact_hall_wave(jmode, branch):
+    # 32 nodes per wavelength, b0 = 0.1, amplitude 1e-3, nu = eta = 0.01, d_i = 2, 200 steps
+    eu, eb = _wave_error(32, 200, 1e-3, 0.1, 2.0, branch=branch, jmode=jmode)
+    tol = TOL_WAVE[jmode] * (1.0 if branch > 0 else 2.5)
+    assert eu < tol and eb < tol, (eu, eb)
+
+
+@pytest.mark.parametrize("jmode", ["stencil", "moment"])
+def test_second_order_convergence_diffusive_scaling(jmode):
+    # diffusive scaling from (N=32, b0=0.1, a=1e-3, d_i=2, 200 steps): k b0, k a, k d_i and
+    # nu k^2 t fixed; the fitted slope of the error against N must be close to -2
+    Ns = [16, 32, 64]
+    errs = []
+    for N in Ns:
+        s = N / 32
+        eu, eb = _wave_error(N, int(round(200 * s * s)), 1e-3 / s, 0.1 / s, 2.0 * s, jmode=jmode)
+        errs.append(max(eu, eb))
+    slope = np.polyfit(np.log(Ns), np.log(errs), 1)[0]
+    assert slope < -1.8, (errs, slope)
+
+
+def test_translation_invariance():
+    # a z-wave on an (nx, ny) = (3, 2) cross-section evolves as on (1, 1), to rounding
+    p1, s1 = _wave_run(16, 30, 1e-3, 0.1, 2.0, jmode="stencil")
+    p2, s2 = _wave_run(16, 30, 1e-3, 0.1, 2.0, jmode="stencil", nx=3, ny=2)
+    assert (s2.f - s1.f).abs().max() < 1e-15
+    assert (s2.g - s1.g).abs().max() < 1e-15
+
+
+def _turbulent_state(n=8, jmode="moment", d_i=2.0, forced=False, seed=0):
+    shape = (n, n, n)
+    u, gu = synthetic.evaluate(synthetic.shell_field(seed, 1, 2, 0.02), shape)
+    b, gb = synthetic.evaluate(synthetic.shell_field(seed + 1, 1, 2, 0.02), shape)
+    fu = fb = None
+    if forced:
+        fu, _ = synthetic.evaluate(synthetic.shell_field(seed + 2, 0, 2, 1e-4, "radius"), shape, gradient=False)
+        fb, _ = synthetic.evaluate(synthetic.shell_field(seed + 3, 0, 2, 1e-4, "radius"), shape, gradient=False)
+        fu = fu + torch.tensor([2e-5, -1e-5, 3e-5], dtype=torch.float64).view(3, 1, 1, 1)
+        fb = fb + torch.tensor([-1e-5, 2e-5, 1e-5], dtype=torch.float64).view(3, 1, 1, 1)
+    p = scheme.Params(n, n, n, 0.02, 0.03, d_i, (0.01, -0.02, 0.05), jmode, "closed", fu, fb)
+    return p, scheme.init_state(p, u, b, gu, gb)
+
+
+@pytest.mark.parametrize("jmode", ["moment", "stencil"])
+def test_invariants_unforced(jmode):
+    p, st = _turbulent_state(jmode=jmode)
+    r0 = diagnostics.reductions(st, p)
+    st = scheme.step(st, p, 10)
+    r1 = diagnostics.reductions(st, p)
+    assert abs(r1[9] - r0[9]) < 1e-13 * r0[9]                    # mass
+    assert (r1[10:13] - r0[10:13]).abs().max() < 1e-13 * r0[9]    # momentum
+    assert (r1[13:16] - r0[13:16]).abs().max() < 1e-13 * r0[9]    # total field
+
+
+def test_invariants_forced():
+    p, st = _turbulent_state(forced=True)
+    r0 = diagnostics.reductions(st, p)
+    steps = 7
+    st = scheme.step(st, p, steps)
+    r1 = diagnostics.reductions(st, p)
+    assert abs(r1[9] - r0[9]) < 1e-13 * r0[9]
+    assert torch.allclose(r1[10:13] - r0[10:13], steps * p.force_u.sum((1, 2, 3)), atol=1e-13, rtol=1e-12)
+    assert torch.allclose(r1[13:16] - r0[13:16], steps * p.force_b.sum((1, 2, 3)), atol=1e-13, rtol=1e-12)
+
+
+def test_uniform_force_accelerates_linearly():
+    # a uniform force on a uniform fluid: U(t) = F t / rho exactly
+    shape = (2, 2, 2)
+    F = torch.tensor([1e-5, -2e-5, 3e-6], dtype=torch.float64).view(3, 1, 1, 1).expand(3, *shape).clone()
+    p = scheme.Params(2, 2, 2, 0.05, 0.05, 0.0, (0.0, 0.0, 0.0), "moment", "closed", F, None)
+    z = torch.zeros((3,) + shape, dtype=torch.float64)
+    st = scheme.init_state(p, z, z)
+    st = scheme.step(st, p, 13)
+    _, U, _, _, _ = scheme.fields(st, p)
+    assert torch.allclose(U, 13 * F, rtol=1e-12, atol=0)
+
+
+def _kolmogorov_error(N, magnetic=False):
+    # steady response to a static sinusoidal source: u = F0 sin(k y) / (nu k^2) x_hat, or with a
+    # magnetic source and no flow coupling (d_i = 0, tiny amplitude) B = S0 sin(k y) / (eta k^2)
+    k = 2 * math.pi / N
+    y = torch.arange(N, dtype=torch.float64).view(1, 1, N, 1)
+    src = torch.zeros(3, 1, N, 1, dtype=torch.float64)
+    nu = 0.1
+    amp = 1e-7
+    src[0] = amp * torch.sin(k * y[0])
+    fu, fb = (None, src) if magnetic else (src, None)
+    p = scheme.Params(1, N, 1, nu, nu, 0.0, (0.0, 0.0, 0.0), "moment", "closed", fu, fb)
+    z = torch.zeros((3, 1, N, 1), dtype=torch.float64)
+    st = scheme.init_state(p, z, z)
+    st = scheme.step(st, p, int(12 / (nu * k * k)))
+    _, U, B, _, _ = scheme.fields(st, p)
+    got = (B if magnetic else U)[0, 0, :, 0]
+    want = amp * torch.sin(k * y[0, 0, :, 0]) / (nu * k * k)
+    return float(torch.linalg.norm(got - want) / torch.linalg.norm(want))
+
+
+@pytest.mark.parametrize("magnetic", [False, True])
+def test_forced_steady_state(magnetic):
+    e16, e32 = _kolmogorov_error(16, magnetic), _kolmogorov_error(32, magnetic)
+    assert e32 < 0.01
+    assert e16 / e32 > 3.0          # second order in k
+
+
+def test_initial_state_moments():
+    n = 8
+    shape = (n, n, n)
+    uf, bf = synthetic.shell_field(4, 1, 2, 0.02), synthetic.shell_field(5, 1, 2, 0.03)
+    u, gu = synthetic.evaluate(uf, shape)
+    b, gb = synthetic.evaluate(bf, shape)
+    p = scheme.Params(n, n, n, 0.01, 0.02, 3.0, (0.0, 0.1, 0.0), "moment", "T")
+    st = scheme.init_state(p, u, b, gu, gb)
+    rho, U, B, Lam = scheme.moments(st, p)
+    B0 = torch.tensor(p.b0, dtype=torch.float64).view(3, 1, 1, 1)
+    assert (rho - 1).abs().max() < 1e-15
+    assert (U - u).abs().max() < 1e-16
+    assert (B - b - B0).abs().max() < 1e-16
+    J = scheme.curl_from_gradient(gb)
+    V = U - p.d_i * J
+    lam0 = torch.einsum("a...,b...->ab...", V, B) - torch.einsum("a...,b...->ab...", B, V)
+    assert (Lam - lam0 + (C2 / p.omega_b) * gb).abs().max() < 1e-16
+    # the moment route then recovers J = curl B exactly at t = 0
+    _, _, _, Jm, _ = scheme.fields(st, p)
+    assert (Jm - J).abs().max() < 1e-13
+    # deviatoric non-equilibrium second central moment of the fluid
+    from oracle.equilibrium import f_mhd_eq
+    fneq = st.f - f_mhd_eq(rho, U, B)
+    cb = C.view(27, 3, 1, 1, 1) - U.unsqueeze(0)
+    K = torch.einsum("iabcd,iebcd,ibcd->aebcd", cb, cb, fneq)
+    s = gu + gu.transpose(0, 1)
+    div = gu[0, 0] + gu[1, 1] + gu[2, 2]
+    P = -(CS2 / p.omega) * (s - (2.0 / 3.0) * div * torch.eye(3, dtype=torch.float64).view(3, 3, 1, 1, 1))
+    assert (K - P).abs().max() < 1e-15
+
+
+def test_xia_density_fluctuation_level():
+    # Sec. 4.2: relative density fluctuations of order 1e-7..1e-6 at Ma 0.003..0.01;
+    # here N = 16, Ma = 0.007, eps_H = 1 (d_i = N cells), nu = 1e-3 in units of U0 N,
+    # b = alpha_+ u + U0 z_hat
+    N = 16
+    ma = 0.007
+    u0 = ma / math.sqrt(3)
+    d_i = float(N)
+    nu = 1e-3 * u0 * N
+    k = 2 * math.pi * 2 / N
+    ap = analytic.beta(d_i, k, +1)        # lattice-unit alpha_+ makes each mode an exact wave
+    uf = synthetic.xia_field(u0)
+    u, gu = synthetic.evaluate(uf, (N, N, N))
+    b, gb = synthetic.evaluate(synthetic.scaled(uf, ap), (N, N, N))
+    p = scheme.Params(N, N, N, nu, nu, d_i, (0.0, 0.0, u0), "moment", "closed")
+    st = scheme.init_state(p, u, b, gu, gb)
+    drho = []
+    for _ in range(6):
+        st = scheme.step(st, p, 25)
+        drho.append(float(diagnostics.reductions(st, p)[7]))
+    level = float(np.mean(drho))
+    assert 1e-8 < level < 1e-5, drho
+
+
+def test_spectrum_parseval_and_single_mode():
+    n = 12
+    f = synthetic.shell_field(9, 1, 3, 0.05)
+    v, _ = synthetic.evaluate(f, (n, n, n), gradient=False)
+    e = diagnostics.spectrum(v, diagnostics.max_shell((n, n, n)))
+    assert abs(e.sum() - 0.5 * float((v * v).sum(0).mean())) < 1e-16
+    w = synthetic.wave_field(0.3, kz=2)
+    v, _ = synthetic.evaluate(w, (n, n, n), gradient=False)
+    e = diagnostics.spectrum(v, 6)
+    assert abs(e[2] - 0.5 * 0.3 ** 2) < 1e-15 and abs(e.sum() - e[2]) < 1e-15
