@@ -1,0 +1,178 @@
+/*
+ * flame.h - C ABI of the MI355X library for the coupled Hall-MHD lattice-Boltzmann step
+ * (Foldes et al., "Efficient kinetic Lattice Boltzmann simulation of three-dimensional
+ * Hall-MHD turbulence", Sec. 3 and App. A-B).
+ *
+ * One step updates, at every node of a periodic nx x ny x nz grid (lattice units,
+ * dx = dt = 1):
+ *   - D3Q27 fluid populations f_i with the central-moment collision of Sec. 3.1.2 towards
+ *     the sixth-order Hermite equilibrium upgraded by the Maxwell stress (App. A);
+ *   - D3Q7 vector magnetic populations g_i (7 x 3) with the BGK collision of Sec. 3.2
+ *     towards the Hall equilibrium (eq. gHall_eq), J taken either from the magnetic
+ *     moments (eq. soe_current_density) or from the central-difference curl of B;
+ *   - streaming of both sets along their lattice velocities.
+ * Relaxation rates follow the paper: 1/omega = 3 nu + 1/2, 1/omega_B = 4 eta + 1/2.
+ *
+ * Conventions shared by every entry point
+ *   - Node index: cell = (z * ny + y) * nx + x.
+ *   - Canonical population order: fluid i = 0..26 in the App. A listing of c_i; magnetic
+ *     directions rest, -x, -y, -z, +x, +y, +z, each with components x, y, z.
+ *     A canonical population array is double [27][nz][ny][nx] followed by
+ *     double [7][3][nz][ny][nx] (48 * ncell doubles), holding the post-streaming,
+ *     pre-collision values of the current time (full values, not deviations).
+ *   - Vector fields are double [3][nz][ny][nx]; gradients double [3][3][nz][ny][nx] with
+ *     grad[a][b] = d field_b / d x_a.
+ *   - "device" pointers are HIP device memory of the device current when flame_init was
+ *     called; "host" pointers are ordinary host memory. The caller owns every buffer it
+ *     passes; the library never frees caller memory.
+ *   - All device work is enqueued on the stream given to flame_init, in order. Entry
+ *     points that return host data synchronise that stream first; asynchronous kernel
+ *     failures surface there as FLAME_E_HIP.
+ *   - Status codes: 0 OK, negative = error (nothing was enqueued unless stated),
+ *     positive = warning flags (the call completed).
+ *   - A context is not thread-safe; calls on one context must not overlap.
+ */
+#ifndef FLAME_H
+#define FLAME_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t flame_status;
+#define FLAME_OK 0
+#define FLAME_E_INVAL (-1)       /* invalid argument; message in flame_last_error */
+#define FLAME_E_NOMEM (-2)       /* library scratch allocation failed */
+#define FLAME_E_HIP (-3)         /* a HIP / hipFFT call failed (message names it) */
+#define FLAME_E_NONFINITE (-4)   /* a population is NaN or infinite (flame_reduce) */
+#define FLAME_E_UNSUPPORTED (-5) /* option combination not built */
+#define FLAME_W_CFL 1            /* advisory whistler bound pi * d_i * max|B| > 1 exceeded */
+
+/* Storage precision of the populations. Values are stored as deviations from the rest
+ * state f^mhd(0)(1, 0, b0), g = W_i b0; F16 additionally scales each deviation by an exact
+ * power of two per velocity class. Collision arithmetic is FP64 for F64, FP32 otherwise. */
+#define FLAME_F64 0
+#define FLAME_F32 1
+#define FLAME_F16 2
+
+/* How J enters the Hall equilibrium. */
+#define FLAME_J_MOMENT 0   /* 3x3 solve from the magnetic first moment (Sec. 3.2) */
+#define FLAME_J_STENCIL 1  /* central-difference curl of B over the six face neighbours */
+
+/* Population layout in the caller's storage buffer.
+ * AB: two lattices for each set, push streaming.
+ * AA: one lattice updated in place (even/odd step addressing); with FLAME_J_STENCIL the
+ *     magnetic set keeps two lattices so that neighbour fields are read-only in a step. */
+#define FLAME_LAYOUT_AB 0
+#define FLAME_LAYOUT_AA 1
+
+/* Reduction slots of flame_reduce (FP64):
+ *  0 E_kin = 1/2 <|u|^2>        1 E_mag = 1/2 <|B - b0|^2>     2 H_c = <u . (B - b0)>
+ *  3 <|J|^2>                    4 max |div B|                  5 rms div B
+ *  6 max |u|                    7 rms (rho - 1)                8 nodes with a non-finite value
+ *  9 sum rho                   10-12 sum rho u                13-15 sum B
+ * div B is the moment estimate -(omega_B / C^2) Tr Lambda of eq. LB_B_div; <.> is the node
+ * average. u and B include the forcing half-shifts F/(2 rho) and S/2. */
+#define FLAME_NRED 16
+
+typedef struct {
+  int32_t nx, ny, nz;   /* grid; each >= 1 (>= 3 with FLAME_J_STENCIL); nx*ny*nz < 2^40 */
+  double nu;            /* lattice kinematic viscosity, > 0 */
+  double eta;           /* lattice resistivity, > 0 */
+  double d_i;           /* Hall coefficient alpha_H in cells (ion inertial length, rho0 = 1), >= 0 */
+  double b0[3];         /* uniform background field */
+  int32_t storage;      /* FLAME_F64 / FLAME_F32 / FLAME_F16 */
+  int32_t jmode;        /* FLAME_J_MOMENT / FLAME_J_STENCIL */
+  int32_t layout;       /* FLAME_LAYOUT_AB / FLAME_LAYOUT_AA */
+  int32_t init_noneq;   /* 1: add the first-order non-equilibrium parts at initialisation */
+  /* Optional static body force F on the fluid and solenoidal source S on the field
+   * (device, [3][nz][ny][nx], double for FLAME_F64 and float otherwise, nullable; must
+   * stay valid while the context lives). Each step adds F to the momentum and S to B. */
+  const void* force_u;
+  const void* force_b;
+} flame_params;
+
+typedef struct flame_ctx flame_ctx;
+
+/* Bytes of population storage the caller must provide for these parameters (0 if the
+ * parameters are invalid). AB: 96 values per node; AA: 48 (69 with FLAME_J_STENCIL);
+ * values are 8, 4 or 2 bytes. */
+size_t flame_storage_bytes(const flame_params* p);
+
+/* Rest state the stored deviations are measured from (host, no device use):
+ * f_rest[27] = f^mhd(0)(1, 0, b0) (App. A equilibrium with the Maxwell stress of b0) and
+ * g_rest[21] = W_i b0 (index i * 3 + component). Either pointer may be NULL. */
+flame_status flame_rest_populations(const flame_params* p, double* f_rest, double* g_rest);
+
+/* Create a context over caller-owned population storage and fill it with the initial state
+ * (paper: rho = 1 everywhere, Sec. 4.1): f = f^mhd(0)(1, u, B), g = g^Hall(0)(u, B, curl B),
+ * plus, if init_noneq and the gradients are given, the first-order non-equilibrium parts
+ * (deviatoric stress -(c_s^2/omega)(grad u + grad u^T - 2/3 div u I) and magnetic
+ * -(1/omega_B) W_i xi_ia d_a B_b). With forcing, -F/2 and -S/2 shifts make the node moments
+ * return exactly u and B = b0 + b.
+ *   u, b: device double [3][nz][ny][nx] (velocity; field fluctuation, B = b0 + b).
+ *   grad_u, grad_b: device double [3][3][nz][ny][nx] or NULL (then no non-equilibrium part
+ *     and J = 0 in the initial Hall equilibrium).
+ *   storage: device, at least flame_storage_bytes(p) bytes, 256-byte aligned.
+ *   hip_stream: hipStream_t (NULL = default stream).
+ * Returns FLAME_OK or FLAME_W_CFL with *out set; on error *out is NULL. */
+flame_status flame_init(const flame_params* p, const double* u, const double* b,
+                        const double* grad_u, const double* grad_b, void* storage,
+                        size_t storage_bytes, void* hip_stream, flame_ctx** out);
+
+/* Advance nsteps >= 0 time steps (one fused kernel launch per step), asynchronously. */
+flame_status flame_step(flame_ctx* c, int64_t nsteps);
+
+/* Node fields of the current state into nullable device double buffers:
+ * rho [nz][ny][nx]; u, b (full B), j [3][nz][ny][nx]; divb [nz][ny][nx]. J is the one the
+ * next step would use (moment or stencil route). Asynchronous. */
+flame_status flame_moments(flame_ctx* c, double* rho, double* u, double* b, double* j,
+                           double* divb);
+
+/* FP64 global reductions (slots above) into host out[FLAME_NRED]. Synchronises. Returns
+ * FLAME_E_NONFINITE (after filling out) if any population is non-finite. Fixed-order
+ * tree sums: bitwise reproducible for a given grid and state. */
+flame_status flame_reduce(flame_ctx* c, double* out);
+
+/* Shell energy spectrum of u (field = 0) or B (field = 1) into host e_k[nshells]:
+ * E(s) = 1/2 sum_{round(|k|) = s} |v_hat(k)|^2, v_hat = DFT(v) / ncell, k the signed integer
+ * wavevector (paper Sec. 4.4 spectra). FP64 FFT (hipFFT) and binning. Synchronises. */
+flame_status flame_spectrum(flame_ctx* c, int32_t field, int32_t nshells, double* e_k);
+
+/* Copy the state in canonical order to / from device double dst/src [48 * ncell].
+ * deviations = 0: full population values; deviations = 1: departures from the rest state of
+ * flame_rest_populations, which are the stored values exactly (decoded), so a get / set pair
+ * with deviations = 1 restores a bitwise-identical state (checkpoint / resume).
+ * flame_set_populations may be called at any time; it leaves the context at an even step and
+ * resets the step count to 0. Both are asynchronous. */
+flame_status flame_get_populations(flame_ctx* c, double* dst, int32_t deviations);
+flame_status flame_set_populations(flame_ctx* c, const double* src, int32_t deviations);
+
+/* Canonical populations of n given nodes: cells (device int64 [n], linear node indices)
+ * -> out (device double [n][48]: 27 fluid then 7 x 3 magnetic; full values or deviations as
+ * above; NaN rows for indices outside the grid). Asynchronous. */
+flame_status flame_gather(flame_ctx* c, const int64_t* cells, int64_t n, double* out,
+                          int32_t deviations);
+
+/* Number of steps taken since flame_init / flame_set_populations. */
+int64_t flame_step_count(const flame_ctx* c);
+
+/* Advisory whistler CFL number pi * d_i * max|B| of the initial state. */
+double flame_cfl_number(const flame_ctx* c);
+
+/* Message of the last error on this context ("" if none); c may be NULL for errors from
+ * flame_init. The pointer stays valid until the next call on the context. */
+const char* flame_last_error(const flame_ctx* c);
+
+/* Release the context and the library's scratch buffers (never the caller's storage).
+ * Synchronises the stream first. */
+void flame_destroy(flame_ctx* c);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FLAME_H */

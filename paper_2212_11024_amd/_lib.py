@@ -1,0 +1,164 @@
+"""ctypes binding of libflame.so: the C entry points of include/flame.h under the same names.
+
+Argument marshalling only; every step of the computation runs in the HIP library. Loading
+fails loudly when the library has not been built.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libflame.so")
+
+FLAME_OK = 0
+FLAME_E_INVAL = -1
+FLAME_E_NOMEM = -2
+FLAME_E_HIP = -3
+FLAME_E_NONFINITE = -4
+FLAME_E_UNSUPPORTED = -5
+FLAME_W_CFL = 1
+
+FLAME_F64, FLAME_F32, FLAME_F16 = 0, 1, 2
+FLAME_J_MOMENT, FLAME_J_STENCIL = 0, 1
+FLAME_LAYOUT_AB, FLAME_LAYOUT_AA = 0, 1
+FLAME_NRED = 16
+
+
+class flame_params(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("nu", ctypes.c_double), ("eta", ctypes.c_double), ("d_i", ctypes.c_double),
+        ("b0", ctypes.c_double * 3),
+        ("storage", ctypes.c_int32), ("jmode", ctypes.c_int32), ("layout", ctypes.c_int32),
+        ("init_noneq", ctypes.c_int32),
+        ("force_u", ctypes.c_void_p), ("force_b", ctypes.c_void_p),
+    ]
+
+
+_P = ctypes.c_void_p
+_SIGNATURES = {
+    "flame_storage_bytes": (ctypes.c_size_t, [ctypes.POINTER(flame_params)]),
+    "flame_rest_populations": (ctypes.c_int32, [ctypes.POINTER(flame_params), ctypes.POINTER(ctypes.c_double),
+                                                ctypes.POINTER(ctypes.c_double)]),
+    "flame_init": (ctypes.c_int32, [ctypes.POINTER(flame_params), _P, _P, _P, _P, _P, ctypes.c_size_t, _P,
+                                    ctypes.POINTER(_P)]),
+    "flame_step": (ctypes.c_int32, [_P, ctypes.c_int64]),
+    "flame_moments": (ctypes.c_int32, [_P, _P, _P, _P, _P, _P]),
+    "flame_reduce": (ctypes.c_int32, [_P, ctypes.POINTER(ctypes.c_double)]),
+    "flame_spectrum": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
+    "flame_get_populations": (ctypes.c_int32, [_P, _P, ctypes.c_int32]),
+    "flame_set_populations": (ctypes.c_int32, [_P, _P, ctypes.c_int32]),
+    "flame_gather": (ctypes.c_int32, [_P, _P, ctypes.c_int64, _P, ctypes.c_int32]),
+    "flame_step_count": (ctypes.c_int64, [_P]),
+    "flame_cfl_number": (ctypes.c_double, [_P]),
+    "flame_last_error": (ctypes.c_char_p, [_P]),
+    "flame_destroy": (None, [_P]),
+}
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libflame.so (once). Raises RuntimeError if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2212_11024_amd.build`")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in _SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+class FlameError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"flame status {code}: {msg}")
+        self.code = code
+
+
+def _check(code: int, ctx=None) -> int:
+    if code < 0:
+        msg = load().flame_last_error(ctx)
+        raise FlameError(code, msg.decode() if msg else "")
+    return code
+
+
+# ---------------------------------------------------------------- entry points (same names)
+
+def flame_storage_bytes(params: flame_params) -> int:
+    return int(load().flame_storage_bytes(ctypes.byref(params)))
+
+
+def flame_rest_populations(params: flame_params):
+    """(f_rest[27], g_rest[21]) as lists of floats."""
+    f = (ctypes.c_double * 27)()
+    g = (ctypes.c_double * 21)()
+    _check(load().flame_rest_populations(ctypes.byref(params), f, g))
+    return list(f), list(g)
+
+
+def flame_init(params: flame_params, u: int, b: int, grad_u: int, grad_b: int, storage: int,
+               storage_bytes: int, stream: int) -> tuple[int, int]:
+    """Returns (status, ctx); raises FlameError on a negative status."""
+    out = _P()
+    code = load().flame_init(ctypes.byref(params), u, b, grad_u, grad_b, storage, storage_bytes, stream,
+                             ctypes.byref(out))
+    _check(code, None)
+    return code, out.value
+
+
+def flame_step(ctx: int, nsteps: int) -> int:
+    return _check(load().flame_step(ctx, nsteps), ctx)
+
+
+def flame_moments(ctx: int, rho: int, u: int, b: int, j: int, divb: int) -> int:
+    return _check(load().flame_moments(ctx, rho, u, b, j, divb), ctx)
+
+
+def flame_reduce(ctx: int, allow_nonfinite: bool = False):
+    out = (ctypes.c_double * FLAME_NRED)()
+    code = load().flame_reduce(ctx, out)
+    if not (allow_nonfinite and code == FLAME_E_NONFINITE):
+        _check(code, ctx)
+    return code, list(out)
+
+
+def flame_spectrum(ctx: int, field: int, nshells: int):
+    out = (ctypes.c_double * nshells)()
+    _check(load().flame_spectrum(ctx, field, nshells, out), ctx)
+    return list(out)
+
+
+def flame_get_populations(ctx: int, dst: int, deviations: int = 0) -> int:
+    return _check(load().flame_get_populations(ctx, dst, deviations), ctx)
+
+
+def flame_set_populations(ctx: int, src: int, deviations: int = 0) -> int:
+    return _check(load().flame_set_populations(ctx, src, deviations), ctx)
+
+
+def flame_gather(ctx: int, cells: int, n: int, out: int, deviations: int = 0) -> int:
+    return _check(load().flame_gather(ctx, cells, n, out, deviations), ctx)
+
+
+def flame_step_count(ctx: int) -> int:
+    return int(load().flame_step_count(ctx))
+
+
+def flame_cfl_number(ctx: int) -> float:
+    return float(load().flame_cfl_number(ctx))
+
+
+def flame_last_error(ctx) -> str:
+    msg = load().flame_last_error(ctx)
+    return msg.decode() if msg else ""
+
+
+def flame_destroy(ctx: int) -> None:
+    load().flame_destroy(ctx)

@@ -1,0 +1,825 @@
+// C ABI of the library (include/flame.h): validation, buffer bookkeeping, the initial
+// state, canonical access, node fields, FP64 reductions and shell spectra.
+
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "flame_internal.h"
+
+namespace flame {
+
+// Rest populations f^mhd(0)(1, 0, b0), passed to kernels by value.
+struct Rest {
+  double f[27];
+  double b0[3];
+};
+
+// ------------------------------------------------------------------ canonical view
+// Read access to the current state in canonical order, for the auxiliary kernels. Returns
+// decoded deviations as double.
+template <typename S>
+struct View {
+  const S* F;
+  const S* G;
+  bool f_odd;   // fluid in place and at an odd step: slot opp(i) at x - c_i
+  bool g_odd;
+  int nx, ny, nz;
+  size_t n;
+
+  __device__ size_t node(int x, int y, int z) const {
+    return (static_cast<size_t>(z) * ny + y) * nx + x;
+  }
+  __device__ double f(int i, int x, int y, int z) const {
+    size_t idx = f_odd ? static_cast<size_t>(oppq(i)) * n +
+                             node(wrap(x - cq(i, 0), nx), wrap(y - cq(i, 1), ny), wrap(z - cq(i, 2), nz))
+                       : static_cast<size_t>(i) * n + node(x, y, z);
+    return static_cast<double>(F[idx]) / Enc<S>::fscale(i);
+  }
+  __device__ double g(int i, int c, int x, int y, int z) const {
+    size_t idx = g_odd ? static_cast<size_t>(oppm(i) * 3 + c) * n +
+                             node(wrap(x - xim(i, 0), nx), wrap(y - xim(i, 1), ny), wrap(z - xim(i, 2), nz))
+                       : static_cast<size_t>(i * 3 + c) * n + node(x, y, z);
+    return static_cast<double>(G[idx]) / Enc<S>::mscale(i);
+  }
+};
+
+// Node quantities in FP64 from the canonical view.
+struct NodeQ {
+  double rho, U[3], B[3], b[3], J[3], divb;
+  bool finite;
+};
+
+template <typename S>
+struct AuxArgs {
+  View<S> v;
+  const typename Enc<S>::R* force_u;
+  const typename Enc<S>::R* force_b;
+  double b0[3];
+  double alpha, omega_b;
+  int stencil;
+};
+
+template <typename S>
+__device__ double field_fluct(const AuxArgs<S>& a, int comp, int x, int y, int z) {
+  double s = a.v.g(0, comp, x, y, z);
+  for (int i = 1; i < 7; ++i) s += a.v.g(i, comp, x, y, z);
+  if (a.force_b) s += 0.5 * static_cast<double>(a.force_b[static_cast<size_t>(comp) * a.v.n + a.v.node(x, y, z)]);
+  return s;
+}
+
+template <typename S>
+__device__ NodeQ node_quantities(const AuxArgs<S>& a, int x, int y, int z) {
+  NodeQ q;
+  const View<S>& v = a.v;
+  const size_t cell = v.node(x, y, z);
+  double f[kQ], g[kM];
+  bool fin = true;
+  for (int i = 0; i < kQ; ++i) {
+    f[i] = v.f(i, x, y, z);
+    fin = fin && isfinite(f[i]);
+  }
+  for (int i = 0; i < 7; ++i)
+    for (int c = 0; c < 3; ++c) {
+      g[i * 3 + c] = v.g(i, c, x, y, z);
+      fin = fin && isfinite(g[i * 3 + c]);
+    }
+  q.finite = fin;
+  double drho = 0, j[3] = {0, 0, 0};
+  for (int i = 0; i < kQ; ++i) {
+    drho += f[i];
+    for (int c = 0; c < 3; ++c) j[c] += cq(i, c) * f[i];
+  }
+  q.rho = 1.0 + drho;
+  for (int c = 0; c < 3; ++c) {
+    const double F = a.force_u ? static_cast<double>(a.force_u[static_cast<size_t>(c) * v.n + cell]) : 0.0;
+    q.U[c] = (j[c] + 0.5 * F) / q.rho;
+  }
+  double lam[3][3];
+  double bb[3];
+  magnetic_moments(g, bb, lam);
+  for (int c = 0; c < 3; ++c) {
+    const double src = a.force_b ? static_cast<double>(a.force_b[static_cast<size_t>(c) * v.n + cell]) : 0.0;
+    q.b[c] = bb[c] + 0.5 * src;
+    q.B[c] = a.b0[c] + q.b[c];
+  }
+  if (!a.stencil) {
+    current_from_moments(lam, q.U, q.B, a.alpha, a.omega_b, q.J);
+  } else {
+    const int xp = wrap(x + 1, v.nx), xm = wrap(x - 1, v.nx);
+    const int yp = wrap(y + 1, v.ny), ym = wrap(y - 1, v.ny);
+    const int zp = wrap(z + 1, v.nz), zm = wrap(z - 1, v.nz);
+    q.J[0] = 0.5 * (field_fluct(a, 2, x, yp, z) - field_fluct(a, 2, x, ym, z))
+           - 0.5 * (field_fluct(a, 1, x, y, zp) - field_fluct(a, 1, x, y, zm));
+    q.J[1] = 0.5 * (field_fluct(a, 0, x, y, zp) - field_fluct(a, 0, x, y, zm))
+           - 0.5 * (field_fluct(a, 2, xp, y, z) - field_fluct(a, 2, xm, y, z));
+    q.J[2] = 0.5 * (field_fluct(a, 1, xp, y, z) - field_fluct(a, 1, xm, y, z))
+           - 0.5 * (field_fluct(a, 0, x, yp, z) - field_fluct(a, 0, x, ym, z));
+  }
+  q.divb = -4.0 * a.omega_b * (lam[0][0] + lam[1][1] + lam[2][2]);
+  return q;
+}
+
+__device__ __forceinline__ void node_xyz(size_t cell, int nx, int ny, int& x, int& y, int& z) {
+  x = static_cast<int>(cell % nx);
+  const size_t r = cell / nx;
+  y = static_cast<int>(r % ny);
+  z = static_cast<int>(r / ny);
+}
+
+// ------------------------------------------------------------------ initial state
+template <typename S>
+struct InitArgs {
+  using R = typename Enc<S>::R;
+  S* F;
+  S* G;
+  const double* u;
+  const double* b;
+  const double* gu;   // [3][3][n] or null
+  const double* gb;
+  const R* force_u;
+  const R* force_b;
+  double b0[3];
+  double omega, omega_b, alpha;
+  int noneq;
+  int nx, ny, nz;
+  size_t n;
+};
+
+template <typename S>
+__global__ __launch_bounds__(256) void init_kernel(InitArgs<S> a) {
+  using E = Enc<S>;
+  const size_t cell = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (cell >= a.n) return;
+  const size_t n = a.n;
+  double U[3], b[3], B[3], F[3] = {0, 0, 0}, Sb[3] = {0, 0, 0};
+  for (int c = 0; c < 3; ++c) {
+    U[c] = a.u[c * n + cell];
+    b[c] = a.b[c * n + cell];
+    B[c] = a.b0[c] + b[c];
+    if (a.force_u) F[c] = static_cast<double>(a.force_u[c * n + cell]);
+    if (a.force_b) Sb[c] = static_cast<double>(a.force_b[c * n + cell]);
+  }
+  double gu[3][3] = {}, gb[3][3] = {};
+  if (a.gu)
+    for (int p = 0; p < 3; ++p)
+      for (int q = 0; q < 3; ++q) gu[p][q] = a.gu[(p * 3 + q) * n + cell];
+  if (a.gb)
+    for (int p = 0; p < 3; ++p)
+      for (int q = 0; q < 3; ++q) gb[p][q] = a.gb[(p * 3 + q) * n + cell];
+
+  // fluid: equilibrium at rho = 1, deviatoric first-order stress, and -F/2 first moment.
+  // These are the post-collision closed-form pieces with (1 - omega) P replaced by the
+  // initial non-equilibrium stress P0 and +F/2 by -F/2.
+  double P[3][3] = {};
+  if (a.noneq && a.gu) {
+    const double div = gu[0][0] + gu[1][1] + gu[2][2];
+    const double s = -(1.0 / 3.0) / a.omega;
+    for (int p = 0; p < 3; ++p)
+      for (int q = 0; q < 3; ++q)
+        P[p][q] = s * (gu[p][q] + gu[q][p] - (p == q ? 2.0 / 3.0 * div : 0.0));
+  }
+  const Axis<double> ax(U[0]), ay(U[1]), az(U[2]);
+  const double s = a.b0[0] * b[0] + a.b0[1] * b[1] + a.b0[2] * b[2]
+                 + 0.5 * (b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+  for (int i = 0; i < kQ; ++i) {
+    const int x = cq(i, 0) + 1, y = cq(i, 1) + 1, z = cq(i, 2) + 1;
+    const double ex = ax.e[x], ey = ay.e[y], ez = az.e[z];
+    const double em1 = ex + (1.0 + ex) * (ey + (1.0 + ey) * ez);
+    const double w = wq(i);
+    double v = w * em1;
+    const double bc = cq(i, 0) * b[0] + cq(i, 1) * b[1] + cq(i, 2) * b[2];
+    const double b0c = cq(i, 0) * a.b0[0] + cq(i, 1) * a.b0[1] + cq(i, 2) * a.b0[2];
+    v += w * 4.5 * (s * (speed2q(i) - 1.0 / 3.0) - bc * (2.0 * b0c + bc));
+    const double h0x = ax.h0[x], h0y = ay.h0[y], h0z = az.h0[z];
+    const double h1x = ax.h1[x], h1y = ay.h1[y], h1z = az.h1[z];
+    const double h2x = ax.h2[x], h2y = ay.h2[y], h2z = az.h2[z];
+    v += P[0][0] * h2x * h0y * h0z + P[1][1] * h0x * h2y * h0z + P[2][2] * h0x * h0y * h2z
+       + P[0][1] * h1x * h1y * h0z + P[0][2] * h1x * h0y * h1z + P[1][2] * h0x * h1y * h1z;
+    v -= 0.5 * (F[0] * h1x * h0y * h0z + F[1] * h0x * h1y * h0z + F[2] * h0x * h0y * h1z);
+    a.F[static_cast<size_t>(i) * n + cell] = E::enc(v, E::fscale(i));
+  }
+  // magnetic: Hall equilibrium with J = curl b, first-order non-equilibrium, -S/2
+  double J[3] = {0, 0, 0};
+  if (a.gb) {
+    J[0] = gb[1][2] - gb[2][1];
+    J[1] = gb[2][0] - gb[0][2];
+    J[2] = gb[0][1] - gb[1][0];
+  }
+  const double V[3] = {U[0] - a.alpha * J[0], U[1] - a.alpha * J[1], U[2] - a.alpha * J[2]};
+  for (int i = 0; i < 7; ++i) {
+    for (int c = 0; c < 3; ++c) {
+      double xv = 0, xb = 0, xg = 0;
+      for (int p = 0; p < 3; ++p) {
+        xv += xim(i, p) * V[p];
+        xb += xim(i, p) * B[p];
+        xg += xim(i, p) * gb[p][c];
+      }
+      double v = wm(i) * (b[c] + 4.0 * (xv * B[c] - xb * V[c]));
+      if (a.noneq && a.gb) v -= wm(i) * xg / a.omega_b;
+      v -= 0.5 * wm(i) * Sb[c];
+      a.G[static_cast<size_t>(i * 3 + c) * n + cell] = E::enc(v, E::mscale(i));
+    }
+  }
+}
+
+// ------------------------------------------------------------------ canonical copies
+template <typename S>
+__global__ __launch_bounds__(256) void get_kernel(View<S> v, Rest r, double* dst) {
+  const size_t cell = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (cell >= v.n) return;
+  int x, y, z;
+  node_xyz(cell, v.nx, v.ny, x, y, z);
+  for (int i = 0; i < kQ; ++i) dst[static_cast<size_t>(i) * v.n + cell] = r.f[i] + v.f(i, x, y, z);
+  for (int i = 0; i < 7; ++i)
+    for (int c = 0; c < 3; ++c)
+      dst[(27 + static_cast<size_t>(i * 3 + c)) * v.n + cell] = wm(i) * r.b0[c] + v.g(i, c, x, y, z);
+}
+
+template <typename S>
+__global__ __launch_bounds__(256) void set_kernel(S* F, S* G, size_t n, Rest r, const double* src) {
+  using E = Enc<S>;
+  const size_t cell = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (cell >= n) return;
+  for (int i = 0; i < kQ; ++i)
+    F[static_cast<size_t>(i) * n + cell] = E::enc(src[static_cast<size_t>(i) * n + cell] - r.f[i], E::fscale(i));
+  for (int i = 0; i < 7; ++i)
+    for (int c = 0; c < 3; ++c) {
+      const size_t k = static_cast<size_t>(i * 3 + c);
+      G[k * n + cell] = E::enc(src[(27 + k) * n + cell] - wm(i) * r.b0[c], E::mscale(i));
+    }
+}
+
+template <typename S>
+__global__ __launch_bounds__(256) void gather_kernel(View<S> v, Rest r, const int64_t* cells, int64_t cnt,
+                                                     double* out) {
+  const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= cnt) return;
+  const int64_t cell = cells[k];
+  if (cell < 0 || static_cast<size_t>(cell) >= v.n) {
+    for (int q = 0; q < 48; ++q) out[k * 48 + q] = NAN;
+    return;
+  }
+  int x, y, z;
+  node_xyz(static_cast<size_t>(cell), v.nx, v.ny, x, y, z);
+  for (int i = 0; i < kQ; ++i) out[k * 48 + i] = r.f[i] + v.f(i, x, y, z);
+  for (int i = 0; i < 7; ++i)
+    for (int c = 0; c < 3; ++c) out[k * 48 + 27 + i * 3 + c] = wm(i) * r.b0[c] + v.g(i, c, x, y, z);
+}
+
+// ------------------------------------------------------------------ node fields
+template <typename S>
+__global__ __launch_bounds__(256) void moments_kernel(AuxArgs<S> a, double* rho, double* u, double* B,
+                                                      double* J, double* divb) {
+  const size_t cell = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (cell >= a.v.n) return;
+  int x, y, z;
+  node_xyz(cell, a.v.nx, a.v.ny, x, y, z);
+  const NodeQ q = node_quantities(a, x, y, z);
+  const size_t n = a.v.n;
+  if (rho) rho[cell] = q.rho;
+  if (divb) divb[cell] = q.divb;
+  for (int c = 0; c < 3; ++c) {
+    if (u) u[c * n + cell] = q.U[c];
+    if (B) B[c * n + cell] = q.B[c];
+    if (J) J[c * n + cell] = q.J[c];
+  }
+}
+
+// ------------------------------------------------------------------ reductions
+constexpr int kRedThreads = 256;
+constexpr int kRedBlocksMax = 2048;
+
+// Per-block partials: sums in every slot except 4 and 6 (maxima). Fixed grid and a fixed
+// tree order make the result bitwise reproducible.
+template <typename S>
+__global__ __launch_bounds__(kRedThreads) void reduce_kernel(AuxArgs<S> a, double* partials) {
+  double acc[FLAME_NRED];
+  for (int k = 0; k < FLAME_NRED; ++k) acc[k] = 0.0;
+  const size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
+  for (size_t cell = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; cell < a.v.n; cell += stride) {
+    int x, y, z;
+    node_xyz(cell, a.v.nx, a.v.ny, x, y, z);
+    const NodeQ q = node_quantities(a, x, y, z);
+    const double u2 = q.U[0] * q.U[0] + q.U[1] * q.U[1] + q.U[2] * q.U[2];
+    acc[0] += 0.5 * u2;
+    acc[1] += 0.5 * (q.b[0] * q.b[0] + q.b[1] * q.b[1] + q.b[2] * q.b[2]);
+    acc[2] += q.U[0] * q.b[0] + q.U[1] * q.b[1] + q.U[2] * q.b[2];
+    acc[3] += q.J[0] * q.J[0] + q.J[1] * q.J[1] + q.J[2] * q.J[2];
+    acc[4] = fmax(acc[4], fabs(q.divb));
+    acc[5] += q.divb * q.divb;
+    acc[6] = fmax(acc[6], sqrt(u2));
+    acc[7] += (q.rho - 1.0) * (q.rho - 1.0);
+    acc[8] += q.finite ? 0.0 : 1.0;
+    acc[9] += q.rho;
+    for (int c = 0; c < 3; ++c) {
+      acc[10 + c] += q.rho * q.U[c];
+      acc[13 + c] += q.B[c];
+    }
+  }
+  __shared__ double sh[FLAME_NRED][kRedThreads];
+  for (int k = 0; k < FLAME_NRED; ++k) sh[k][threadIdx.x] = acc[k];
+  __syncthreads();
+  for (int s = kRedThreads / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      for (int k = 0; k < FLAME_NRED; ++k) {
+        const double o = sh[k][threadIdx.x + s];
+        sh[k][threadIdx.x] = (k == 4 || k == 6) ? fmax(sh[k][threadIdx.x], o) : sh[k][threadIdx.x] + o;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < FLAME_NRED) partials[blockIdx.x * FLAME_NRED + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// ------------------------------------------------------------------ spectra
+template <typename S>
+__global__ __launch_bounds__(256) void field_component_kernel(AuxArgs<S> a, int field, int comp, double* out) {
+  const size_t cell = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (cell >= a.v.n) return;
+  int x, y, z;
+  node_xyz(cell, a.v.nx, a.v.ny, x, y, z);
+  const View<S>& v = a.v;
+  if (field == 0) {
+    double drho = 0, j = 0;
+    for (int i = 0; i < kQ; ++i) {
+      const double fi = v.f(i, x, y, z);
+      drho += fi;
+      j += cq(i, comp) * fi;
+    }
+    const double F = a.force_u ? static_cast<double>(a.force_u[comp * v.n + cell]) : 0.0;
+    out[cell] = (j + 0.5 * F) / (1.0 + drho);
+  } else {
+    out[cell] = a.b0[comp] + field_fluct(a, comp, x, y, z);
+  }
+}
+
+constexpr int kSpecThreads = 256;
+constexpr int kSpecShellsMax = 4096;
+
+__device__ __forceinline__ int signed_freq(int idx, int n) { return idx <= (n - 1) / 2 ? idx : idx - n; }
+
+// Half-spectrum (nz, ny, nx/2+1) of an r2c transform; each entry stands for itself and, for
+// 0 < kx < nx - kx, its conjugate mirror at -k (same shell).
+__global__ __launch_bounds__(kSpecThreads) void shell_bin_kernel(const hipfftDoubleComplex* X, int nx, int ny,
+                                                                 int nz, int nshells, double norm2,
+                                                                 double* partials) {
+  extern __shared__ double bins[];
+  for (int s = threadIdx.x; s < nshells; s += blockDim.x) bins[s] = 0.0;
+  __syncthreads();
+  const int nxh = nx / 2 + 1;
+  const size_t total = static_cast<size_t>(nz) * ny * nxh;
+  const size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
+  for (size_t k = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; k < total; k += stride) {
+    const int kx = static_cast<int>(k % nxh);
+    const size_t r = k / nxh;
+    const int ky = static_cast<int>(r % ny);
+    const int kz = static_cast<int>(r / ny);
+    const double fx = kx, fy = signed_freq(ky, ny), fz = signed_freq(kz, nz);
+    const int shell = static_cast<int>(floor(sqrt(fx * fx + fy * fy + fz * fz) + 0.5));
+    if (shell >= nshells) continue;
+    const double re = X[k].x, im = X[k].y;
+    const double mult = (kx == 0 || 2 * kx == nx) ? 1.0 : 2.0;
+    atomicAdd(&bins[shell], mult * 0.5 * (re * re + im * im) * norm2);
+  }
+  __syncthreads();
+  for (int s = threadIdx.x; s < nshells; s += blockDim.x) partials[static_cast<size_t>(blockIdx.x) * nshells + s] = bins[s];
+}
+
+}  // namespace flame
+
+using namespace flame;
+
+// ====================================================================== host side
+namespace {
+
+thread_local std::string g_init_error;
+
+flame_status fail(flame_ctx* c, flame_status code, const std::string& msg) {
+  if (c) c->err = msg; else g_init_error = msg;
+  return code;
+}
+
+#define FLAME_HIP(c, call)                                                        \
+  do {                                                                            \
+    hipError_t e_ = (call);                                                       \
+    if (e_ != hipSuccess)                                                         \
+      return fail((c), FLAME_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+std::string validate(const flame_params* p) {
+  if (!p) return "params is NULL";
+  if (p->nx < 1 || p->ny < 1 || p->nz < 1) return "grid sizes must be >= 1";
+  if (p->jmode == FLAME_J_STENCIL && (p->nx < 3 || p->ny < 3 || p->nz < 3))
+    return "the stencil current needs every grid size >= 3";
+  const double cells = static_cast<double>(p->nx) * p->ny * p->nz;
+  if (cells >= 1099511627776.0) return "grid too large (nx*ny*nz must be < 2^40)";
+  if (p->nz > 65535) return "nz must be <= 65535";
+  if (!(p->nu > 0) || !isfinite(p->nu)) return "nu must be finite and > 0";
+  if (!(p->eta > 0) || !isfinite(p->eta)) return "eta must be finite and > 0";
+  if (!(p->d_i >= 0) || !isfinite(p->d_i)) return "d_i must be finite and >= 0";
+  for (int i = 0; i < 3; ++i)
+    if (!isfinite(p->b0[i])) return "b0 must be finite";
+  if (p->storage != FLAME_F64 && p->storage != FLAME_F32 && p->storage != FLAME_F16)
+    return "unknown storage";
+  if (p->jmode != FLAME_J_MOMENT && p->jmode != FLAME_J_STENCIL) return "unknown jmode";
+  if (p->layout != FLAME_LAYOUT_AB && p->layout != FLAME_LAYOUT_AA) return "unknown layout";
+  return "";
+}
+
+size_t values_per_node(const flame_params& p) {
+  if (p.layout == FLAME_LAYOUT_AB) return 96;
+  return p.jmode == FLAME_J_STENCIL ? 69 : 48;
+}
+
+template <typename S>
+View<S> make_view(const flame_ctx* c) {
+  const SetPtrs s = set_ptrs(c);
+  View<S> v;
+  v.F = static_cast<const S*>(s.f_src);
+  v.G = static_cast<const S*>(s.g_src);
+  v.f_odd = s.fluid_aa && c->parity == 1;
+  v.g_odd = s.mag_aa && c->parity == 1;
+  v.nx = c->p.nx;
+  v.ny = c->p.ny;
+  v.nz = c->p.nz;
+  v.n = c->n;
+  return v;
+}
+
+template <typename S>
+AuxArgs<S> make_aux(const flame_ctx* c) {
+  using R = typename Enc<S>::R;
+  AuxArgs<S> a;
+  a.v = make_view<S>(c);
+  a.force_u = static_cast<const R*>(c->p.force_u);
+  a.force_b = static_cast<const R*>(c->p.force_b);
+  for (int i = 0; i < 3; ++i) a.b0[i] = c->p.b0[i];
+  a.alpha = c->p.d_i;
+  a.omega_b = c->omega_b;
+  a.stencil = c->p.jmode == FLAME_J_STENCIL;
+  return a;
+}
+
+// Rest state for full-value copies; all zeros for deviation copies.
+Rest make_rest(const flame_ctx* c, int32_t deviations) {
+  Rest r;
+  for (int i = 0; i < 27; ++i) r.f[i] = deviations ? 0.0 : c->frest[i];
+  for (int i = 0; i < 3; ++i) r.b0[i] = deviations ? 0.0 : c->p.b0[i];
+  return r;
+}
+
+unsigned blocks_for(size_t n, int threads) { return static_cast<unsigned>((n + threads - 1) / threads); }
+
+// Dispatch a callable templated on the storage type.
+template <typename Fn>
+hipError_t by_storage(const flame_ctx* c, Fn&& fn) {
+  switch (c->p.storage) {
+    case FLAME_F64: return fn(double{});
+    case FLAME_F32: return fn(float{});
+    default: return fn(_Float16{});
+  }
+}
+
+__global__ void max_field_kernel(const double* b, double b0x, double b0y, double b0z, size_t n, double* out) {
+  __shared__ double sh[256];
+  double m = 0.0;
+  for (size_t k = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; k < n;
+       k += static_cast<size_t>(gridDim.x) * blockDim.x) {
+    const double x = b0x + b[k], y = b0y + b[n + k], z = b0z + b[2 * n + k];
+    m = fmax(m, sqrt(x * x + y * y + z * z));
+  }
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = sh[0];
+}
+
+}  // namespace
+
+namespace flame {
+SetPtrs set_ptrs(const flame_ctx* c) {
+  const size_t vb = value_bytes(c->p.storage);
+  const size_t n = c->n;
+  char* base = static_cast<char*>(c->storage);
+  SetPtrs s{};
+  if (c->p.layout == FLAME_LAYOUT_AB) {
+    char* F0 = base;
+    char* F1 = base + 27 * n * vb;
+    char* G0 = base + 54 * n * vb;
+    char* G1 = G0 + 21 * n * vb;
+    s.f_src = c->cur ? F1 : F0;
+    s.f_dst = c->cur ? F0 : F1;
+    s.g_src = c->cur ? G1 : G0;
+    s.g_dst = c->cur ? G0 : G1;
+    s.fluid_aa = false;
+    s.mag_aa = false;
+  } else {
+    s.f_src = s.f_dst = base;
+    s.fluid_aa = true;
+    char* G0 = base + 27 * n * vb;
+    if (c->p.jmode == FLAME_J_STENCIL) {
+      char* G1 = G0 + 21 * n * vb;
+      s.g_src = c->cur ? G1 : G0;
+      s.g_dst = c->cur ? G0 : G1;
+      s.mag_aa = false;
+    } else {
+      s.g_src = s.g_dst = G0;
+      s.mag_aa = true;
+    }
+  }
+  return s;
+}
+}  // namespace flame
+
+extern "C" {
+
+flame_status flame_rest_populations(const flame_params* p, double* f_rest, double* g_rest) {
+  if (!p) return FLAME_E_INVAL;
+  // f^mhd(0)(1, 0, b0) = w_i + (w_i / 2 c_s^4) M(b0) : (c c - c_s^2 I), M = |b0|^2/2 I - b0 b0,
+  // with M : (c c - I/3) = |b0|^2/2 (|c|^2 - 1/3) - (b0 . c)^2
+  const double* B0 = p->b0;
+  const double b2 = B0[0] * B0[0] + B0[1] * B0[1] + B0[2] * B0[2];
+  if (f_rest)
+    for (int i = 0; i < 27; ++i) {
+      const double cb = cq(i, 0) * B0[0] + cq(i, 1) * B0[1] + cq(i, 2) * B0[2];
+      f_rest[i] = wq(i) + wq(i) * 4.5 * (0.5 * b2 * (speed2q(i) - 1.0 / 3.0) - cb * cb);
+    }
+  if (g_rest)
+    for (int i = 0; i < 7; ++i)
+      for (int c = 0; c < 3; ++c) g_rest[i * 3 + c] = wm(i) * B0[c];
+  return FLAME_OK;
+}
+
+size_t flame_storage_bytes(const flame_params* p) {
+  if (!validate(p).empty()) return 0;
+  return values_per_node(*p) * value_bytes(p->storage) * static_cast<size_t>(p->nx) * p->ny * p->nz;
+}
+
+flame_status flame_init(const flame_params* p, const double* u, const double* b, const double* grad_u,
+                        const double* grad_b, void* storage, size_t storage_bytes, void* hip_stream,
+                        flame_ctx** out) {
+  g_init_error.clear();
+  if (!out) return fail(nullptr, FLAME_E_INVAL, "out is NULL");
+  *out = nullptr;
+  const std::string bad = validate(p);
+  if (!bad.empty()) return fail(nullptr, FLAME_E_INVAL, bad);
+  if (!u || !b) return fail(nullptr, FLAME_E_INVAL, "u and b must be given");
+  if (!storage) return fail(nullptr, FLAME_E_INVAL, "storage is NULL");
+  if (reinterpret_cast<uintptr_t>(storage) % 256 != 0) return fail(nullptr, FLAME_E_INVAL, "storage must be 256-byte aligned");
+  const size_t need = flame_storage_bytes(p);
+  if (storage_bytes < need)
+    return fail(nullptr, FLAME_E_INVAL, "storage too small: need " + std::to_string(need) + " bytes");
+  flame_ctx* c = new (std::nothrow) flame_ctx;
+  if (!c) return fail(nullptr, FLAME_E_NOMEM, "context allocation failed");
+  c->p = *p;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  c->n = static_cast<size_t>(p->nx) * p->ny * p->nz;
+  c->storage = storage;
+  c->omega = 1.0 / (3.0 * p->nu + 0.5);
+  c->omega_b = 1.0 / (4.0 * p->eta + 0.5);
+  const double* B0 = p->b0;
+  flame_rest_populations(p, c->frest, nullptr);
+  auto bail = [&](flame_status code) {
+    g_init_error = c->err;
+    delete c;
+    return code;
+  };
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    c->err = "hipGetDevice failed (no HIP device?)";
+    return bail(FLAME_E_HIP);
+  }
+  c->red_blocks = static_cast<int>(std::min<size_t>(kRedBlocksMax, blocks_for(c->n, kRedThreads)));
+  if (hipMalloc(&c->red_partials, sizeof(double) * FLAME_NRED * std::max(c->red_blocks, 1)) != hipSuccess) {
+    c->err = "hipMalloc of reduction scratch failed";
+    return bail(FLAME_E_NOMEM);
+  }
+  // initial state into the canonical slots of copy 0
+  const SetPtrs s = set_ptrs(c);
+  hipError_t e = by_storage(c, [&](auto tag) {
+    using S = decltype(tag);
+    using R = typename Enc<S>::R;
+    InitArgs<S> a;
+    a.F = static_cast<S*>(s.f_src);
+    a.G = static_cast<S*>(s.g_src);
+    a.u = u;
+    a.b = b;
+    a.gu = grad_u;
+    a.gb = grad_b;
+    a.force_u = static_cast<const R*>(p->force_u);
+    a.force_b = static_cast<const R*>(p->force_b);
+    for (int i = 0; i < 3; ++i) a.b0[i] = B0[i];
+    a.omega = c->omega;
+    a.omega_b = c->omega_b;
+    a.alpha = p->d_i;
+    a.noneq = p->init_noneq;
+    a.nx = p->nx;
+    a.ny = p->ny;
+    a.nz = p->nz;
+    a.n = c->n;
+    hipLaunchKernelGGL(init_kernel<S>, dim3(blocks_for(c->n, 256)), dim3(256), 0, c->stream, a);
+    return hipGetLastError();
+  });
+  if (e != hipSuccess) {
+    c->err = std::string("init kernel: ") + hipGetErrorString(e);
+    return bail(FLAME_E_HIP);
+  }
+  // advisory CFL number from max |B| of the initial field
+  const int mb = static_cast<int>(std::min<size_t>(1024, blocks_for(c->n, 256)));
+  hipLaunchKernelGGL(max_field_kernel, dim3(mb), dim3(256), 0, c->stream, b, B0[0], B0[1], B0[2], c->n,
+                     c->red_partials);
+  double host[1024];
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(host, c->red_partials, sizeof(double) * mb, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    c->err = std::string("initial field maximum: ") + hipGetErrorString(e);
+    return bail(FLAME_E_HIP);
+  }
+  double bmax = 0;
+  for (int i = 0; i < mb; ++i) bmax = std::max(bmax, host[i]);
+  c->cfl = M_PI * p->d_i * bmax;
+  *out = c;
+  return c->cfl > 1.0 ? FLAME_W_CFL : FLAME_OK;
+}
+
+flame_status flame_step(flame_ctx* c, int64_t nsteps) {
+  if (!c) return FLAME_E_INVAL;
+  if (nsteps < 0) return fail(c, FLAME_E_INVAL, "nsteps must be >= 0");
+  const bool two_f = c->p.layout == FLAME_LAYOUT_AB;
+  const bool two_g = mag_two_lattice(c->p);
+  for (int64_t s = 0; s < nsteps; ++s) {
+    const SetPtrs ptr = set_ptrs(c);
+    hipError_t e = launch_step(c, ptr);
+    if (e != hipSuccess) return fail(c, FLAME_E_HIP, std::string("step kernel: ") + hipGetErrorString(e));
+    if (two_f || two_g) c->cur ^= 1;
+    if (!two_f || !two_g) c->parity ^= 1;
+    c->steps += 1;
+  }
+  return FLAME_OK;
+}
+
+flame_status flame_moments(flame_ctx* c, double* rho, double* u, double* b, double* j, double* divb) {
+  if (!c) return FLAME_E_INVAL;
+  hipError_t e = by_storage(c, [&](auto tag) {
+    using S = decltype(tag);
+    hipLaunchKernelGGL(moments_kernel<S>, dim3(blocks_for(c->n, 256)), dim3(256), 0, c->stream,
+                       make_aux<S>(c), rho, u, b, j, divb);
+    return hipGetLastError();
+  });
+  if (e != hipSuccess) return fail(c, FLAME_E_HIP, std::string("moments kernel: ") + hipGetErrorString(e));
+  return FLAME_OK;
+}
+
+flame_status flame_reduce(flame_ctx* c, double* out) {
+  if (!c || !out) return c ? fail(c, FLAME_E_INVAL, "out is NULL") : FLAME_E_INVAL;
+  hipError_t e = by_storage(c, [&](auto tag) {
+    using S = decltype(tag);
+    hipLaunchKernelGGL(reduce_kernel<S>, dim3(c->red_blocks), dim3(kRedThreads), 0, c->stream, make_aux<S>(c),
+                       c->red_partials);
+    return hipGetLastError();
+  });
+  if (e != hipSuccess) return fail(c, FLAME_E_HIP, std::string("reduce kernel: ") + hipGetErrorString(e));
+  std::vector<double> host(static_cast<size_t>(c->red_blocks) * FLAME_NRED);
+  FLAME_HIP(c, hipMemcpyAsync(host.data(), c->red_partials, sizeof(double) * FLAME_NRED * c->red_blocks,
+                              hipMemcpyDeviceToHost, c->stream));
+  FLAME_HIP(c, hipStreamSynchronize(c->stream));
+  double acc[FLAME_NRED] = {};
+  for (int blk = 0; blk < c->red_blocks; ++blk)
+    for (int k = 0; k < FLAME_NRED; ++k) {
+      const double v = host[blk * FLAME_NRED + k];
+      acc[k] = (k == 4 || k == 6) ? std::max(acc[k], v) : acc[k] + v;
+    }
+  const double n = static_cast<double>(c->n);
+  out[0] = acc[0] / n;
+  out[1] = acc[1] / n;
+  out[2] = acc[2] / n;
+  out[3] = acc[3] / n;
+  out[4] = acc[4];
+  out[5] = sqrt(acc[5] / n);
+  out[6] = acc[6];
+  out[7] = sqrt(acc[7] / n);
+  for (int k = 8; k < FLAME_NRED; ++k) out[k] = acc[k];
+  if (acc[8] > 0) return fail(c, FLAME_E_NONFINITE, "non-finite populations at " + std::to_string(acc[8]) + " nodes");
+  return FLAME_OK;
+}
+
+flame_status flame_spectrum(flame_ctx* c, int32_t field, int32_t nshells, double* e_k) {
+  if (!c) return FLAME_E_INVAL;
+  if (field != 0 && field != 1) return fail(c, FLAME_E_INVAL, "field must be 0 (u) or 1 (B)");
+  if (nshells < 1 || nshells > kSpecShellsMax) return fail(c, FLAME_E_INVAL, "nshells out of range");
+  if (!e_k) return fail(c, FLAME_E_INVAL, "e_k is NULL");
+  const int nx = c->p.nx, ny = c->p.ny, nz = c->p.nz;
+  const size_t nh = static_cast<size_t>(nz) * ny * (nx / 2 + 1);
+  if (!c->spec_real) {
+    FLAME_HIP(c, hipMalloc(&c->spec_real, sizeof(double) * c->n));
+    FLAME_HIP(c, hipMalloc(&c->spec_cplx, sizeof(hipfftDoubleComplex) * nh));
+  }
+  if (!c->plan_ok) {
+    if (hipfftPlan3d(&c->plan, nz, ny, nx, HIPFFT_D2Z) != HIPFFT_SUCCESS)
+      return fail(c, FLAME_E_HIP, "hipfftPlan3d failed");
+    c->plan_ok = true;
+    if (hipfftSetStream(c->plan, c->stream) != HIPFFT_SUCCESS) return fail(c, FLAME_E_HIP, "hipfftSetStream failed");
+  }
+  const int blocks = static_cast<int>(std::min<size_t>(1024, blocks_for(nh, kSpecThreads)));
+  if (c->spec_blocks != blocks || c->spec_nshells < nshells) {
+    if (c->spec_partials) FLAME_HIP(c, hipFree(c->spec_partials));
+    c->spec_partials = nullptr;
+    FLAME_HIP(c, hipMalloc(&c->spec_partials, sizeof(double) * blocks * nshells));
+    c->spec_blocks = blocks;
+    c->spec_nshells = nshells;
+  }
+  std::vector<double> host(static_cast<size_t>(blocks) * nshells);
+  for (int s = 0; s < nshells; ++s) e_k[s] = 0.0;
+  const double norm2 = 1.0 / (static_cast<double>(c->n) * static_cast<double>(c->n));
+  for (int comp = 0; comp < 3; ++comp) {
+    hipError_t e = by_storage(c, [&](auto tag) {
+      using S = decltype(tag);
+      hipLaunchKernelGGL(field_component_kernel<S>, dim3(blocks_for(c->n, 256)), dim3(256), 0, c->stream,
+                         make_aux<S>(c), field, comp, c->spec_real);
+      return hipGetLastError();
+    });
+    if (e != hipSuccess) return fail(c, FLAME_E_HIP, std::string("field kernel: ") + hipGetErrorString(e));
+    if (hipfftExecD2Z(c->plan, c->spec_real, static_cast<hipfftDoubleComplex*>(c->spec_cplx)) != HIPFFT_SUCCESS)
+      return fail(c, FLAME_E_HIP, "hipfftExecD2Z failed");
+    hipLaunchKernelGGL(shell_bin_kernel, dim3(blocks), dim3(kSpecThreads), sizeof(double) * nshells, c->stream,
+                       static_cast<const hipfftDoubleComplex*>(c->spec_cplx), nx, ny, nz, nshells, norm2,
+                       c->spec_partials);
+    e = hipGetLastError();
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(host.data(), c->spec_partials, sizeof(double) * blocks * nshells, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return fail(c, FLAME_E_HIP, std::string("spectrum: ") + hipGetErrorString(e));
+    for (int blk = 0; blk < blocks; ++blk)
+      for (int s = 0; s < nshells; ++s) e_k[s] += host[static_cast<size_t>(blk) * nshells + s];
+  }
+  return FLAME_OK;
+}
+
+flame_status flame_get_populations(flame_ctx* c, double* dst, int32_t deviations) {
+  if (!c || !dst) return c ? fail(c, FLAME_E_INVAL, "dst is NULL") : FLAME_E_INVAL;
+  hipError_t e = by_storage(c, [&](auto tag) {
+    using S = decltype(tag);
+    hipLaunchKernelGGL(get_kernel<S>, dim3(blocks_for(c->n, 256)), dim3(256), 0, c->stream, make_view<S>(c),
+                       make_rest(c, deviations), dst);
+    return hipGetLastError();
+  });
+  if (e != hipSuccess) return fail(c, FLAME_E_HIP, std::string("get kernel: ") + hipGetErrorString(e));
+  return FLAME_OK;
+}
+
+flame_status flame_set_populations(flame_ctx* c, const double* src, int32_t deviations) {
+  if (!c || !src) return c ? fail(c, FLAME_E_INVAL, "src is NULL") : FLAME_E_INVAL;
+  c->cur = 0;
+  c->parity = 0;
+  c->steps = 0;
+  const SetPtrs s = set_ptrs(c);
+  hipError_t e = by_storage(c, [&](auto tag) {
+    using S = decltype(tag);
+    hipLaunchKernelGGL(set_kernel<S>, dim3(blocks_for(c->n, 256)), dim3(256), 0, c->stream,
+                       static_cast<S*>(s.f_src), static_cast<S*>(s.g_src), c->n, make_rest(c, deviations), src);
+    return hipGetLastError();
+  });
+  if (e != hipSuccess) return fail(c, FLAME_E_HIP, std::string("set kernel: ") + hipGetErrorString(e));
+  return FLAME_OK;
+}
+
+flame_status flame_gather(flame_ctx* c, const int64_t* cells, int64_t n, double* out, int32_t deviations) {
+  if (!c) return FLAME_E_INVAL;
+  if (n < 0 || (n > 0 && (!cells || !out))) return fail(c, FLAME_E_INVAL, "bad gather arguments");
+  if (n == 0) return FLAME_OK;
+  hipError_t e = by_storage(c, [&](auto tag) {
+    using S = decltype(tag);
+    hipLaunchKernelGGL(gather_kernel<S>, dim3(blocks_for(static_cast<size_t>(n), 256)), dim3(256), 0, c->stream,
+                       make_view<S>(c), make_rest(c, deviations), cells, n, out);
+    return hipGetLastError();
+  });
+  if (e != hipSuccess) return fail(c, FLAME_E_HIP, std::string("gather kernel: ") + hipGetErrorString(e));
+  return FLAME_OK;
+}
+
+int64_t flame_step_count(const flame_ctx* c) { return c ? c->steps : -1; }
+
+double flame_cfl_number(const flame_ctx* c) { return c ? c->cfl : 0.0; }
+
+const char* flame_last_error(const flame_ctx* c) { return c ? c->err.c_str() : g_init_error.c_str(); }
+
+void flame_destroy(flame_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  if (c->plan_ok) hipfftDestroy(c->plan);
+  if (c->red_partials) (void)hipFree(c->red_partials);
+  if (c->spec_real) (void)hipFree(c->spec_real);
+  if (c->spec_cplx) (void)hipFree(c->spec_cplx);
+  if (c->spec_partials) (void)hipFree(c->spec_partials);
+  delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,257 @@
+// Device-side lattice tables, storage encodings and per-node arithmetic of the coupled
+// Hall-MHD lattice-Boltzmann step (paper Sec. 3.1-3.2, App. A-B).
+//
+// Populations are carried as deviations from the rest state of the run,
+//   df_i = f_i - f_rest_i,  f_rest = f^mhd(0)(1, 0, b0);   dg_ia = g_ia - W_i b0_a,
+// so that FP32/FP16 storage keeps its precision for the small departures that carry the
+// physics. All per-node arithmetic below is written in terms of these deviations.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace flame {
+
+// ------------------------------------------------------------------ lattice tables
+// D3Q27 velocities in the order of the paper's App. A listing.
+__host__ __device__ constexpr int cq(int i, int a) {
+  constexpr int8_t t[27][3] = {
+      {0, 0, 0},   {-1, 0, 0},  {0, -1, 0},  {0, 0, -1}, {-1, -1, 0}, {-1, 1, 0},  {-1, 0, -1},
+      {-1, 0, 1},  {0, -1, -1}, {0, -1, 1},  {-1, -1, -1}, {-1, -1, 1}, {-1, 1, -1}, {-1, 1, 1},
+      {1, 0, 0},   {0, 1, 0},   {0, 0, 1},   {1, 1, 0},  {1, -1, 0},  {1, 0, 1},   {1, 0, -1},
+      {0, 1, 1},   {0, 1, -1},  {1, 1, 1},   {1, 1, -1}, {1, -1, 1},  {1, -1, -1}};
+  return t[i][a];
+}
+// In the App. A listing the opposite of direction i (1 <= i <= 13) is i + 13.
+__host__ __device__ constexpr int oppq(int i) { return i == 0 ? 0 : (i <= 13 ? i + 13 : i - 13); }
+__host__ __device__ constexpr int speed2q(int i) {
+  return cq(i, 0) * cq(i, 0) + cq(i, 1) * cq(i, 1) + cq(i, 2) * cq(i, 2);
+}
+// Weights by speed class (Sec. 3.1): 8/27, 2/27, 1/54, 1/216.
+__host__ __device__ constexpr double wq(int i) {
+  return speed2q(i) == 0 ? 8.0 / 27.0
+       : speed2q(i) == 1 ? 2.0 / 27.0
+       : speed2q(i) == 2 ? 1.0 / 54.0
+                          : 1.0 / 216.0;
+}
+// D3Q7: rest, -x, -y, -z, +x, +y, +z. Weights 1/4 (rest), 1/8 (faces); C^2 = 1/4.
+__host__ __device__ constexpr int xim(int i, int a) {
+  return i == 0 ? 0 : (i <= 3 ? (a == i - 1 ? -1 : 0) : (a == i - 4 ? 1 : 0));
+}
+__host__ __device__ constexpr int oppm(int i) { return i == 0 ? 0 : (i <= 3 ? i + 3 : i - 3); }
+__host__ __device__ constexpr double wm(int i) { return i == 0 ? 0.25 : 0.125; }
+
+constexpr int kQ = 27;
+constexpr int kM = 21;   // 7 directions x 3 components, index i * 3 + component
+
+// ------------------------------------------------------------------ storage encodings
+// Power-of-two scales applied to stored deviations (exact in every format); only FP16
+// needs them, to keep deviations of magnitude ~ w_i |u| clear of the subnormal range.
+template <typename S>
+struct Enc;
+
+template <>
+struct Enc<double> {
+  using R = double;
+  static __host__ __device__ constexpr double fscale(int) { return 1.0; }
+  static __host__ __device__ constexpr double mscale(int) { return 1.0; }
+  static __device__ __forceinline__ double dec(double v, double) { return v; }
+  static __device__ __forceinline__ double enc(double v, double) { return v; }
+};
+
+template <>
+struct Enc<float> {
+  using R = float;
+  static __host__ __device__ constexpr double fscale(int) { return 1.0; }
+  static __host__ __device__ constexpr double mscale(int) { return 1.0; }
+  static __device__ __forceinline__ float dec(float v, float) { return v; }
+  static __device__ __forceinline__ float enc(float v, float) { return v; }
+};
+
+template <>
+struct Enc<_Float16> {
+  using R = float;
+  static __host__ __device__ constexpr double fscale(int i) {
+    return speed2q(i) == 0 ? 4.0 : speed2q(i) == 1 ? 16.0 : speed2q(i) == 2 ? 64.0 : 256.0;
+  }
+  static __host__ __device__ constexpr double mscale(int i) { return i == 0 ? 4.0 : 8.0; }
+  static __device__ __forceinline__ float dec(_Float16 v, float inv_scale) {
+    return static_cast<float>(v) * inv_scale;
+  }
+  static __device__ __forceinline__ _Float16 enc(float v, float scale) {
+    return static_cast<_Float16>(v * scale);
+  }
+};
+
+// ------------------------------------------------------------------ run constants
+template <typename R>
+struct PhysConst {
+  R omega;       // fluid relaxation rate, 1/omega = 3 nu + 1/2
+  R omega_b;     // magnetic relaxation rate, 1/omega_B = 4 eta + 1/2
+  R alpha;       // Hall coefficient alpha_H (= d_i in cells)
+  R b0[3];       // background field
+};
+
+// ------------------------------------------------------------------ per-node arithmetic
+// Fluid moments of the deviations: d rho = sum df, j = sum df c, S2 = sum df c c.
+template <typename R>
+struct FluidMoments {
+  R drho, jx, jy, jz, sxx, syy, szz, sxy, sxz, syz;
+};
+
+template <typename R>
+__device__ __forceinline__ FluidMoments<R> fluid_moments(const R (&f)[kQ]) {
+  FluidMoments<R> m{};
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) {
+    const R v = f[i];
+    m.drho += v;
+    if (cq(i, 0) == 1) m.jx += v; else if (cq(i, 0) == -1) m.jx -= v;
+    if (cq(i, 1) == 1) m.jy += v; else if (cq(i, 1) == -1) m.jy -= v;
+    if (cq(i, 2) == 1) m.jz += v; else if (cq(i, 2) == -1) m.jz -= v;
+    if (cq(i, 0) != 0) m.sxx += v;
+    if (cq(i, 1) != 0) m.syy += v;
+    if (cq(i, 2) != 0) m.szz += v;
+    if (cq(i, 0) * cq(i, 1) == 1) m.sxy += v; else if (cq(i, 0) * cq(i, 1) == -1) m.sxy -= v;
+    if (cq(i, 0) * cq(i, 2) == 1) m.sxz += v; else if (cq(i, 0) * cq(i, 2) == -1) m.sxz -= v;
+    if (cq(i, 1) * cq(i, 2) == 1) m.syz += v; else if (cq(i, 1) * cq(i, 2) == -1) m.syz -= v;
+  }
+  return m;
+}
+
+// Field fluctuation b = sum dg (the rest part sums to b0) and Lambda_ab = sum_i xi_ia g_ib,
+// which for D3Q7 is the difference of the +a and -a populations (the rest part cancels).
+template <typename R>
+__device__ __forceinline__ void magnetic_moments(const R (&g)[kM], R (&b)[3], R (&lam)[3][3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    R s = g[a];
+#pragma unroll
+    for (int i = 1; i < 7; ++i) s += g[i * 3 + a];
+    b[a] = s;
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) lam[a][c] = g[(4 + a) * 3 + c] - g[(1 + a) * 3 + c];
+}
+
+// J from the magnetic first moment (Sec. 3.2): (I + 2 alpha w_B / C^2 M(B)) J = -(w_B/C^2) J0,
+// M(B) J = J x B, J0 = eps:Lambda - 2 U x B. Written as J + k (J x B) = r, whose solution is
+// J = (r - k r x B + k^2 (r . B) B) / (1 + k^2 |B|^2), with k = 8 alpha w_B and r = -4 w_B J0.
+template <typename R>
+__device__ __forceinline__ void current_from_moments(const R (&lam)[3][3], const R (&U)[3],
+                                                     const R (&B)[3], R alpha, R omega_b,
+                                                     R (&J)[3]) {
+  const R j0x = lam[1][2] - lam[2][1] - R(2) * (U[1] * B[2] - U[2] * B[1]);
+  const R j0y = lam[2][0] - lam[0][2] - R(2) * (U[2] * B[0] - U[0] * B[2]);
+  const R j0z = lam[0][1] - lam[1][0] - R(2) * (U[0] * B[1] - U[1] * B[0]);
+  const R s = R(-4) * omega_b;
+  const R rx = s * j0x, ry = s * j0y, rz = s * j0z;
+  const R k = R(8) * alpha * omega_b;
+  const R rbx = ry * B[2] - rz * B[1], rby = rz * B[0] - rx * B[2], rbz = rx * B[1] - ry * B[0];
+  const R rdb = rx * B[0] + ry * B[1] + rz * B[2];
+  const R k2 = k * k;
+  const R inv = R(1) / (R(1) + k2 * (B[0] * B[0] + B[1] * B[1] + B[2] * B[2]));
+  J[0] = (rx - k * rbx + k2 * rdb * B[0]) * inv;
+  J[1] = (ry - k * rby + k2 * rdb * B[1]) * inv;
+  J[2] = (rz - k * rbz + k2 * rdb * B[2]) * inv;
+}
+
+// 1-D factors on c in {-1, 0, +1} (index c + 1):
+//  e(c) = phi(c; u) / w1(c) - 1, phi the D1Q3 equilibrium (its 3-D product is the
+//        sixth-order Hermite f^(0) of App. A): e(0) = -3u^2/2, e(+-1) = 3u^2 +- 3u;
+//  h_p(c): central moments about u equal to delta_{p,q} for q = 0, 1, 2.
+template <typename R>
+struct Axis {
+  R e[3], h0[3], h1[3], h2[3];
+  __device__ __forceinline__ explicit Axis(R u) {
+    const R u2 = u * u;
+    e[0] = R(3) * (u2 - u); e[1] = R(-1.5) * u2; e[2] = R(3) * (u2 + u);
+    h0[0] = R(0.5) * (u2 - u); h0[1] = R(1) - u2; h0[2] = R(0.5) * (u2 + u);
+    h1[0] = u - R(0.5); h1[1] = R(-2) * u; h1[2] = u + R(0.5);
+    h2[0] = R(0.5); h2[1] = R(-1); h2[2] = R(0.5);
+  }
+};
+
+// Post-collision fluid deviations, in place (Sec. 3.1.2 with S = diag[1,1,1,1,w x5,1 x18]).
+// Because every moment except the five deviatoric second-order ones relaxes to equilibrium
+// with rate 1, the back-transform of the collided central moments is
+//   f*_i = f^mhd(0)_i + (1 - w) sum_ab P_ab H^ab_i + sum_a (F_a/2) H^a_i,
+// with P the deviatoric second central moment of f - f^mhd(0), H^ab = h..(c_x) h..(c_y) h..(c_z)
+// the distributions with a single unit central moment, and F the body force (its half enters
+// the velocity, the collision sets the first central moment to +F/2).
+// In deviations: f^mhd(0)_i - f_rest_i = w_i [d rho E_i + (E_i - 1)] + (w_i / 2 c_s^4)
+// (M(B) - M(b0)) : (c c - c_s^2 I), E_i = prod_a (1 + e_a), M(B) = |B|^2/2 I - B B.
+template <typename R>
+__device__ __forceinline__ void collide_fluid(R (&f)[kQ], const FluidMoments<R>& m, R rho,
+                                              const R (&U)[3], const R (&b)[3], const R (&b0)[3],
+                                              const R (&F)[3], R omega) {
+  // deviatoric K = S2 - rho U U + (U F + F U)/2 + (B B - b0 b0); B B - b0 b0 = b0 b + b b0 + b b
+  const R kxx = m.sxx - rho * U[0] * U[0] + U[0] * F[0] + b[0] * (R(2) * b0[0] + b[0]);
+  const R kyy = m.syy - rho * U[1] * U[1] + U[1] * F[1] + b[1] * (R(2) * b0[1] + b[1]);
+  const R kzz = m.szz - rho * U[2] * U[2] + U[2] * F[2] + b[2] * (R(2) * b0[2] + b[2]);
+  const R om1 = R(1) - omega;
+  const R tr = (kxx + kyy + kzz) * R(1.0 / 3.0);
+  const R qxx = om1 * (kxx - tr), qyy = om1 * (kyy - tr), qzz = om1 * (kzz - tr);
+  const R qxy = om1 * (m.sxy - rho * U[0] * U[1] + R(0.5) * (U[0] * F[1] + F[0] * U[1])
+                       + b0[0] * b[1] + b[0] * b0[1] + b[0] * b[1]);
+  const R qxz = om1 * (m.sxz - rho * U[0] * U[2] + R(0.5) * (U[0] * F[2] + F[0] * U[2])
+                       + b0[0] * b[2] + b[0] * b0[2] + b[0] * b[2]);
+  const R qyz = om1 * (m.syz - rho * U[1] * U[2] + R(0.5) * (U[1] * F[2] + F[1] * U[2])
+                       + b0[1] * b[2] + b[1] * b0[2] + b[1] * b[2]);
+  const R fhx = R(0.5) * F[0], fhy = R(0.5) * F[1], fhz = R(0.5) * F[2];
+  // Maxwell-stress change: (M(B) - M(b0)) : (cc - I/3) = s (|c|^2 - 1/3) - (b.c)(2 b0.c + b.c)
+  const R s = b0[0] * b[0] + b0[1] * b[1] + b0[2] * b[2]
+            + R(0.5) * (b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+  const Axis<R> ax(U[0]), ay(U[1]), az(U[2]);
+  const R drho = m.drho;
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) {
+    const int x = cq(i, 0) + 1, y = cq(i, 1) + 1, z = cq(i, 2) + 1;
+    const R ex = ax.e[x], ey = ay.e[y], ez = az.e[z];
+    const R em1 = ex + (R(1) + ex) * (ey + (R(1) + ey) * ez);   // E_i - 1 without cancellation
+    const R w = R(wq(i));
+    R v = w * (drho * (R(1) + em1) + em1);
+    const R bc = R(cq(i, 0)) * b[0] + R(cq(i, 1)) * b[1] + R(cq(i, 2)) * b[2];
+    const R b0c = R(cq(i, 0)) * b0[0] + R(cq(i, 1)) * b0[1] + R(cq(i, 2)) * b0[2];
+    v += (w * R(4.5)) * (s * R(speed2q(i) - 1.0 / 3.0) - bc * (R(2) * b0c + bc));
+    const R h0x = ax.h0[x], h0y = ay.h0[y], h0z = az.h0[z];
+    const R h1x = ax.h1[x], h1y = ay.h1[y], h1z = az.h1[z];
+    const R h2x = ax.h2[x], h2y = ay.h2[y], h2z = az.h2[z];
+    v += h0z * (h2x * h0y * qxx + h0x * h2y * qyy + h1x * h1y * qxy + h1x * h0y * fhx + h0x * h1y * fhy)
+       + h1z * (h1x * h0y * qxz + h0x * h1y * qyz + h0x * h0y * fhz)
+       + h2z * (h0x * h0y * qzz);
+    f[i] = v;
+  }
+}
+
+// Post-collision magnetic deviations, in place (eq. MHD_LBscheme with the Hall equilibrium
+// gHall_eq): g* = g - w_B (g - g^Hall(0)) + (1 - w_B/2) W_i S. With V = U - alpha J and
+// E_ac = V_a B_c - B_a V_c, g^Hall(0)_{+-a, c} = W (B_c +- 4 E_ac), g^Hall(0)_{0, c} = W_0 B_c.
+template <typename R>
+__device__ __forceinline__ void collide_magnetic(R (&g)[kM], const R (&U)[3], const R (&B)[3],
+                                                 const R (&b)[3], const R (&J)[3],
+                                                 const R (&S)[3], R alpha, R omega_b) {
+  const R V[3] = {U[0] - alpha * J[0], U[1] - alpha * J[1], U[2] - alpha * J[2]};
+  const R src = R(1) - R(0.5) * omega_b;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const R eq0 = R(0.25) * b[c];
+    g[c] = g[c] - omega_b * (g[c] - eq0) + src * R(0.25) * S[c];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const R E = (a == c) ? R(0) : (V[a] * B[c] - B[a] * V[c]);
+      const R eqp = R(0.125) * (b[c] + R(4) * E);
+      const R eqm = R(0.125) * (b[c] - R(4) * E);
+      const int ip = (4 + a) * 3 + c, im = (1 + a) * 3 + c;
+      g[ip] = g[ip] - omega_b * (g[ip] - eqp) + src * R(0.125) * S[c];
+      g[im] = g[im] - omega_b * (g[im] - eqm) + src * R(0.125) * S[c];
+    }
+  }
+}
+
+// Periodic neighbour of a node.
+__device__ __forceinline__ int wrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+}  // namespace flame

@@ -1,0 +1,133 @@
+"""Python-side owner of device buffers around one flame context.
+
+torch supplies device memory (the population storage, fields, forcing) and the stream; all
+arithmetic happens in libflame.so through the entry points of ``_lib``.
+"""
+
+from __future__ import annotations
+
+import torch
+
+from . import _lib as L
+
+STORAGE = {"f64": L.FLAME_F64, "f32": L.FLAME_F32, "f16": L.FLAME_F16}
+JMODE = {"moment": L.FLAME_J_MOMENT, "stencil": L.FLAME_J_STENCIL}
+LAYOUT = {"ab": L.FLAME_LAYOUT_AB, "aa": L.FLAME_LAYOUT_AA}
+
+
+def _ptr(t):
+    return 0 if t is None else t.data_ptr()
+
+
+class Solver:
+    """One periodic nx x ny x nz Hall-MHD LB run on the current HIP device.
+
+    u, b: (3, nz, ny, nx) float64 (velocity; field fluctuation, B = b0 + b).
+    grad_u, grad_b: (3, 3, nz, ny, nx) float64, grad[a, b] = d_a f_b, or None.
+    force_u, force_b: (3, nz, ny, nx) static forcing (any float dtype; converted to the
+    storage's arithmetic type: float64 for "f64", float32 otherwise), or None.
+    """
+
+    def __init__(self, nx, ny, nz, nu, eta, d_i=0.0, b0=(0.0, 0.0, 0.0), storage="f32",
+                 jmode="moment", layout="aa", u=None, b=None, grad_u=None, grad_b=None,
+                 force_u=None, force_b=None, init_noneq=True, device="cuda"):
+        if not torch.cuda.is_available():
+            raise RuntimeError("flame needs a HIP device (torch.cuda.is_available() is False)")
+        L.load()
+        self.device = torch.device(device)
+        self.shape = (nz, ny, nx)
+        self.n = nx * ny * nz
+        ftype = torch.float64 if storage == "f64" else torch.float32
+        self.force_u = None if force_u is None else force_u.to(self.device, ftype).contiguous()
+        self.force_b = None if force_b is None else force_b.to(self.device, ftype).contiguous()
+        p = L.flame_params()
+        p.nx, p.ny, p.nz = nx, ny, nz
+        p.nu, p.eta, p.d_i = nu, eta, d_i
+        for i in range(3):
+            p.b0[i] = float(b0[i])
+        p.storage, p.jmode, p.layout = STORAGE[storage], JMODE[jmode], LAYOUT[layout]
+        p.init_noneq = 1 if init_noneq else 0
+        p.force_u = _ptr(self.force_u) or None
+        p.force_b = _ptr(self.force_b) or None
+        self.params = p
+        nbytes = L.flame_storage_bytes(p)
+        if nbytes == 0:
+            raise L.FlameError(L.FLAME_E_INVAL, "invalid parameters")
+        self.storage = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        if self.storage.data_ptr() % 256:
+            raise RuntimeError("population storage is not 256-byte aligned")
+
+        def dev(t):
+            return None if t is None else t.to(self.device, torch.float64).contiguous()
+
+        zero = torch.zeros((3,) + self.shape, dtype=torch.float64, device=self.device)
+        u = dev(u) if u is not None else zero
+        b = dev(b) if b is not None else zero
+        gu, gb = dev(grad_u), dev(grad_b)
+        self.stream = torch.cuda.current_stream(self.device)
+        self.status, self.ctx = L.flame_init(p, _ptr(u), _ptr(b), _ptr(gu), _ptr(gb), _ptr(self.storage),
+                                             nbytes, self.stream.cuda_stream)
+        self.stream.synchronize()     # the inputs may be released after this point
+
+    # -- time stepping
+    def step(self, n=1):
+        L.flame_step(self.ctx, int(n))
+
+    @property
+    def steps(self):
+        return L.flame_step_count(self.ctx)
+
+    @property
+    def cfl(self):
+        return L.flame_cfl_number(self.ctx)
+
+    # -- diagnostics
+    def fields(self):
+        """rho (nz,ny,nx), u (3,...), B (3,...), J (3,...), div B (nz,ny,nx), float64 on device."""
+        t = lambda *s: torch.empty(s, dtype=torch.float64, device=self.device)  # noqa: E731
+        rho, u, B, J, d = t(*self.shape), t(3, *self.shape), t(3, *self.shape), t(3, *self.shape), t(*self.shape)
+        L.flame_moments(self.ctx, rho.data_ptr(), u.data_ptr(), B.data_ptr(), J.data_ptr(), d.data_ptr())
+        return rho, u, B, J, d
+
+    def reduce(self, allow_nonfinite=False):
+        code, vals = L.flame_reduce(self.ctx, allow_nonfinite)
+        return torch.tensor(vals, dtype=torch.float64)
+
+    def spectrum(self, field, nshells):
+        return torch.tensor(L.flame_spectrum(self.ctx, {"u": 0, "B": 1}.get(field, field), nshells),
+                            dtype=torch.float64)
+
+    # -- canonical state
+    def get_populations(self, deviations=False):
+        """(f (27, nz, ny, nx), g (7, 3, nz, ny, nx)) float64 on device: full values, or the
+        departures from the rest state (the stored values, exactly) with deviations=True."""
+        out = torch.empty(48 * self.n, dtype=torch.float64, device=self.device)
+        L.flame_get_populations(self.ctx, out.data_ptr(), int(deviations))
+        return out[: 27 * self.n].view(27, *self.shape), out[27 * self.n:].view(7, 3, *self.shape)
+
+    def set_populations(self, f, g, deviations=False):
+        src = torch.cat([f.reshape(-1), g.reshape(-1)]).to(self.device, torch.float64).contiguous()
+        L.flame_set_populations(self.ctx, src.data_ptr(), int(deviations))
+        self.stream.synchronize()
+
+    def gather(self, cells, deviations=False):
+        """Canonical populations (k, 48) float64 at linear node indices ``cells``."""
+        cells = torch.as_tensor(cells, dtype=torch.int64, device=self.device).contiguous()
+        out = torch.empty((cells.numel(), 48), dtype=torch.float64, device=self.device)
+        L.flame_gather(self.ctx, cells.data_ptr(), cells.numel(), out.data_ptr(), int(deviations))
+        return out
+
+    def rest_populations(self):
+        f, g = L.flame_rest_populations(self.params)
+        return (torch.tensor(f, dtype=torch.float64), torch.tensor(g, dtype=torch.float64).view(7, 3))
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            L.flame_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

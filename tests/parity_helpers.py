@@ -1,0 +1,107 @@
+"""Shared helpers for the GPU-vs-oracle parity tests: seeded inputs fed to both sides and
+the deviation-norm comparison. Imports the oracle (test infrastructure) and the product
+binding side by side; neither imports the other."""
+
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+import torch
+
+import synthetic
+from oracle import extended, scheme
+
+
+@dataclasses.dataclass
+class Case:
+    nx: int
+    ny: int
+    nz: int
+    nu: float = 0.02
+    eta: float = 0.03
+    d_i: float = 2.0
+    b0: tuple = (0.01, -0.02, 0.05)
+    jmode: str = "moment"
+    rms: float = 0.02
+    forced: bool = False
+    seed: int = 0
+    kmax: int = 2
+
+    @property
+    def shape(self):
+        return (self.nx, self.ny, self.nz)
+
+
+def inputs(case: Case, device="cpu"):
+    """u, grad u, b, grad b, F, S (float64) on ``device``; F, S are None when unforced."""
+    km = min(case.kmax, (min(case.shape) - 1) // 2)
+    u, gu = synthetic.evaluate(synthetic.shell_field(case.seed, 1, km, case.rms), case.shape, device)
+    b, gb = synthetic.evaluate(synthetic.shell_field(case.seed + 1, 1, km, case.rms), case.shape, device)
+    fu = fb = None
+    if case.forced:
+        fu, _ = synthetic.evaluate(synthetic.shell_field(case.seed + 2, 0, 1, 1e-4, "radius"), case.shape, device,
+                                   gradient=False)
+        fb, _ = synthetic.evaluate(synthetic.shell_field(case.seed + 3, 0, 1, 1e-4, "radius"), case.shape, device,
+                                   gradient=False)
+    return u, gu, b, gb, fu, fb
+
+
+def oracle_params(case: Case, fu=None, fb=None, route="closed"):
+    return scheme.Params(case.nx, case.ny, case.nz, case.nu, case.eta, case.d_i, case.b0, case.jmode, route,
+                         fu, fb)
+
+
+def oracle_run(case: Case, steps: int, route="closed", noneq=True, ftype=torch.float64):
+    """Oracle state after ``steps`` from the seeded inputs (forcing cast through ftype so both
+    sides see the same forcing values)."""
+    u, gu, b, gb, fu, fb = inputs(case)
+    if fu is not None:
+        fu = fu.to(ftype).to(torch.float64)
+        fb = fb.to(ftype).to(torch.float64)
+    p = oracle_params(case, fu, fb, route)
+    st = scheme.init_state(p, u, b, gu, gb, noneq=noneq)
+    return p, scheme.step(st, p, steps)
+
+
+def gpu_solver(case: Case, storage="f64", layout="aa", noneq=True):
+    from paper_2212_11024_amd.solver import Solver
+    u, gu, b, gb, fu, fb = inputs(case)
+    return Solver(case.nx, case.ny, case.nz, case.nu, case.eta, case.d_i, case.b0, storage, case.jmode, layout,
+                  u, b, gu, gb, fu, fb, init_noneq=noneq)
+
+
+def deviation_error(solver, p, st):
+    """Relative L2 error of the GPU populations against the FP64 oracle state, both measured
+    as deviations from the rest state f^mhd(0)(1, 0, b0), g = W b0, over all 48 arrays."""
+    rest = scheme.rest_state(p)
+    df, dg = solver.get_populations(deviations=True)
+    of = st.f - rest.f
+    og = st.g - rest.g
+    num = ((df.cpu() - of) ** 2).sum() + ((dg.cpu() - og) ** 2).sum()
+    den = (of ** 2).sum() + (og ** 2).sum()
+    return float((num / den).sqrt())
+
+
+def extended_run(case: Case, steps: int, ftype=torch.float64, noneq=True):
+    """The same run in extended precision: (deviation f, deviation g) as longdouble arrays."""
+    u, gu, b, gb, fu, fb = inputs(case)
+    if fu is not None:
+        fu = fu.to(ftype).to(torch.float64)
+        fb = fb.to(ftype).to(torch.float64)
+    xp = extended.Params(oracle_params(case, fu, fb))
+    f, g = extended.init_state(xp, u, b, gu, gb, noneq=noneq)
+    f, g = extended.step(f, g, xp, steps)
+    fr, gr = extended.rest_state(xp, f.shape[1:])
+    return f - fr, g - gr
+
+
+def extended_error(solver, ref):
+    """Relative L2 error of the GPU deviations against an extended-precision reference."""
+    xf, xg = ref
+    df, dg = solver.get_populations(deviations=True)
+    df = df.cpu().numpy().astype(np.longdouble)
+    dg = dg.cpu().numpy().astype(np.longdouble)
+    num = ((df - xf) ** 2).sum() + ((dg - xg) ** 2).sum()
+    den = (xf ** 2).sum() + (xg ** 2).sum()
+    return float(np.sqrt(num / den))
