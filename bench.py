@@ -1,0 +1,192 @@
+"""Benchmark of the fused Hall-MHD lattice-Boltzmann step on one MI355X.
+
+Workload (forced Hall-MHD turbulence, 512^3): periodic 512^3 grid, FP32 populations stored as
+deviations from rest (FP32 collision arithmetic); seeded random-phase solenoidal u and b with a
+flat spectrum in shells 1 <= |k| <= 4, rms u = rms b = 0.02; static solenoidal forcing of u
+and B at 0 < |k| <= 2 with rms 1e-5 each; nu = eta = 0.001; d_i = 4 cells; b0 = 0; J by the
+curl stencil; fluid populations updated in place (AA), magnetic ones double-buffered.
+
+One step = one launch of the fused kernel over the whole grid (all of the hot path: loads,
+moments, J, both collisions, streaming stores). The timed region holds exactly --steps steps,
+bracketed by device synchronisation; the inputs are resident in HBM before it starts.
+
+Prints one JSON line. Besides the headline (FP32, stencil J) it reports the same workload with
+the moment-route J and with FP64 storage, the roofline of the headline kernel (algorithmic
+bytes per launch over the event-timed average launch), and the CPU oracle timed on a bounded
+sample on the host cores.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0        # MI355X HBM3E peak
+WORKLOAD = "forced Hall-MHD turbulence 512^3 (FP32 deviation storage, FP64 reductions)"
+
+
+def workload_fields(n, device):
+    """Seeded inputs of the forced-turbulence workload on an n^3 grid (float64 on device)."""
+    import synthetic
+    shape = (n, n, n)
+    u, gu = synthetic.evaluate(synthetic.shell_field(0, 1, 4, 0.02), shape, device)
+    b, gb = synthetic.evaluate(synthetic.shell_field(1, 1, 4, 0.02), shape, device)
+    fu, _ = synthetic.evaluate(synthetic.shell_field(2, 0, 2, 1e-5, "radius"), shape, device, gradient=False)
+    fb, _ = synthetic.evaluate(synthetic.shell_field(3, 0, 2, 1e-5, "radius"), shape, device, gradient=False)
+    return u, gu, b, gb, fu, fb
+
+
+PHYS = dict(nu=0.001, eta=0.001, d_i=4.0, b0=(0.0, 0.0, 0.0))
+
+
+def make_solver(n, storage="f32", jmode="stencil", layout="aa", device="cuda", fields=None):
+    import torch
+    from paper_2212_11024_amd.solver import Solver
+    u, gu, b, gb, fu, fb = fields if fields is not None else workload_fields(n, device)
+    s = Solver(n, n, n, PHYS["nu"], PHYS["eta"], PHYS["d_i"], PHYS["b0"], storage, jmode, layout,
+               u, b, gu, gb, fu, fb, device=device)
+    torch.cuda.synchronize()
+    return s
+
+
+def bytes_per_node(storage, forced=True):
+    """Algorithmic HBM bytes per node update: read and write 27 + 21 populations, plus the
+    static forcing fields (3 + 3 values in the arithmetic type) when forced."""
+    vb = {"f64": 8, "f32": 4, "f16": 2}[storage]
+    fb = 8 if storage == "f64" else 4
+    return 2 * 48 * vb + (6 * fb if forced else 0)
+
+
+def time_variant(n, storage, jmode, steps, warmup, fields):
+    import torch
+    s = make_solver(n, storage, jmode, "aa", fields=fields)
+    s.step(warmup)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    stream = torch.cuda.current_stream()
+    t0 = time.perf_counter()
+    start.record(stream)
+    s.step(steps)
+    end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = start.elapsed_time(end) / steps
+    red = s.reduce(allow_nonfinite=True)
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    nodes = n ** 3
+    bpn = bytes_per_node(storage)
+    return {
+        "storage": storage, "jmode": jmode, "ms_per_step": ms, "wall_s": wall,
+        "mlups": nodes / (ms * 1e-3) / 1e6,
+        "bytes_per_node": bpn,
+        "achieved_GBps": bpn * nodes / (ms * 1e-3) / 1e9,
+        "E_kin": float(red[0]), "E_mag": float(red[1]), "nonfinite_nodes": int(red[8]),
+    }
+
+
+def cpu_baseline(seconds=15.0):
+    """The FP64 oracle (closed-form route, as it stands) on a 32^3 sample of the workload's
+    physics, on the host cores; MLUPS = nodes x steps / time."""
+    import torch
+    from oracle import scheme
+    torch.set_num_threads(int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
+    n = 32
+    u, gu, b, gb, fu, fb = workload_fields(n, "cpu")
+    p = scheme.Params(n, n, n, PHYS["nu"], PHYS["eta"], PHYS["d_i"], PHYS["b0"], "stencil", "closed", fu, fb)
+    st = scheme.init_state(p, u, b, gu, gb)
+    st = scheme.step(st, p, 1)                  # warm-up
+    steps, t0 = 0, time.perf_counter()
+    while True:
+        st = scheme.step(st, p, 1)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    return {"value": n ** 3 * steps / el / 1e6, "unit": "MLUPS", "cores": torch.get_num_threads(),
+            "kind": "oracle",
+            "sample": f"32^3 nodes, {steps} steps of the workload physics (stencil J, forced), "
+                      f"FP64 closed-form route, {el:.1f} s"}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--size", type=int, default=512)
+    ap.add_argument("--variants", default="all", help="all | headline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU slab "
+              "decomposition is a design, not a build, in this version", file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_2212_11024_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2212_11024_amd.build import build
+        build()
+    torch.cuda.set_device(0)
+    n = args.size
+    fields = workload_fields(n, "cuda")
+    torch.cuda.synchronize()
+    variants = [("f32", "stencil")]
+    if args.variants == "all":
+        variants += [("f32", "moment"), ("f64", "stencil"), ("f16", "stencil")]
+    results = []
+    for storage, jmode in variants:
+        print(f"[bench] {n}^3 {storage} {jmode}: {args.warmup} warm-up + {args.steps} timed steps", file=sys.stderr,
+              flush=True)
+        r = time_variant(n, storage, jmode, args.steps, args.warmup, fields)
+        print(f"[bench]   {r['ms_per_step']:.3f} ms/step, {r['mlups']:.0f} MLUPS, {r['achieved_GBps']:.0f} GB/s",
+              file=sys.stderr, flush=True)
+        results.append(r)
+    del fields
+    torch.cuda.empty_cache()
+    head = results[0]
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(args.cpu_seconds)
+    line = {
+        "metric": "MLUPS & HBM GB/s (% of peak) FP32 vs FP64 at 512^3; adjoint/forward time ratio",
+        "value": round(head["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(head["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded Fourier-mode fields)",
+        "config": {"workload": WORKLOAD if n == 512 else WORKLOAD.replace("512^3", f"{n}^3"),
+                   "grid": [n, n, n], "nu": PHYS["nu"], "eta": PHYS["eta"], "d_i": PHYS["d_i"],
+                   "j_mode": "stencil", "layout": "aa (fluid in place, magnetic double-buffered)",
+                   "forcing": "static, |k| <= 2, rms 1e-5"},
+        "roofline": {"bound": "hbm", "achieved": round(head["achieved_GBps"], 1), "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": round(head["achieved_GBps"] / HBM_PEAK_GBPS, 4), "traffic": None,
+                     "bytes_per_node": head["bytes_per_node"]},
+        "variants": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()} for r in results],
+        "adjoint_forward_ratio": None,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
