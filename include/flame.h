@@ -79,7 +79,8 @@ typedef int32_t flame_status;
 #define FLAME_NRED 16
 
 typedef struct {
-  int32_t nx, ny, nz;   /* grid; each >= 1 (>= 3 with FLAME_J_STENCIL); nx*ny*nz < 2^40 */
+  int32_t nx, ny, nz;   /* grid; each >= 1 (>= 3 with FLAME_J_STENCIL), nz <= 65535; one population
+                           array (nx*ny*nz values) and one forcing array must each fit in 4 GiB */
   double nu;            /* lattice kinematic viscosity, > 0 */
   double eta;           /* lattice resistivity, > 0 */
   double d_i;           /* Hall coefficient alpha_H in cells (ion inertial length, rho0 = 1), >= 0 */

@@ -26,25 +26,45 @@ template <typename S>
 struct View {
   const S* F;
   const S* G;
-  bool f_odd;   // fluid in place and at an odd step: slot opp(i) at x - c_i
-  bool g_odd;
+  // addressing of the canonical population i at node x:
+  //   0: slot i at x (AA even step); 1: slot opp(i) at x - c_i (AA odd step);
+  //   2: slot i at x - c_i (two-lattice pull: the source copy holds post-collision values)
+  int fmode;
+  int gmode;
   int nx, ny, nz;
   size_t n;
+  size_t stride;   // elements between population arrays
 
   __device__ size_t node(int x, int y, int z) const {
     return (static_cast<size_t>(z) * ny + y) * nx + x;
   }
   __device__ double f(int i, int x, int y, int z) const {
-    size_t idx = f_odd ? static_cast<size_t>(oppq(i)) * n +
-                             node(wrap(x - cq(i, 0), nx), wrap(y - cq(i, 1), ny), wrap(z - cq(i, 2), nz))
-                       : static_cast<size_t>(i) * n + node(x, y, z);
+    size_t idx = fmode == 0 ? static_cast<size_t>(i) * stride + node(x, y, z)
+                            : static_cast<size_t>(fmode == 1 ? oppq(i) : i) * stride +
+                                  node(wrap(x - cq(i, 0), nx), wrap(y - cq(i, 1), ny), wrap(z - cq(i, 2), nz));
     return static_cast<double>(F[idx]) / Enc<S>::fscale(i);
   }
   __device__ double g(int i, int c, int x, int y, int z) const {
-    size_t idx = g_odd ? static_cast<size_t>(oppm(i) * 3 + c) * n +
-                             node(wrap(x - xim(i, 0), nx), wrap(y - xim(i, 1), ny), wrap(z - xim(i, 2), nz))
-                       : static_cast<size_t>(i * 3 + c) * n + node(x, y, z);
+    size_t idx = gmode == 0 ? static_cast<size_t>(i * 3 + c) * stride + node(x, y, z)
+                            : static_cast<size_t>((gmode == 1 ? oppm(i) : i) * 3 + c) * stride +
+                                  node(wrap(x - xim(i, 0), nx), wrap(y - xim(i, 1), ny), wrap(z - xim(i, 2), nz));
     return static_cast<double>(G[idx]) / Enc<S>::mscale(i);
+  }
+};
+
+// Where a writer of the canonical state (initial state, set) puts population i of node
+// (x, y, z): its own slot for in-place sets; for pull sets the slot at x - c_i, which is where
+// the next step at node x pulls population i from.
+struct Placement {
+  bool fpull, gpull;
+  int nx, ny, nz;
+  __device__ size_t f(int i, int x, int y, int z) const {
+    if (fpull) { x = wrap(x - cq(i, 0), nx); y = wrap(y - cq(i, 1), ny); z = wrap(z - cq(i, 2), nz); }
+    return (static_cast<size_t>(z) * ny + y) * nx + x;
+  }
+  __device__ size_t g(int i, int x, int y, int z) const {
+    if (gpull) { x = wrap(x - xim(i, 0), nx); y = wrap(y - xim(i, 1), ny); z = wrap(z - xim(i, 2), nz); }
+    return (static_cast<size_t>(z) * ny + y) * nx + x;
   }
 };
 
@@ -148,6 +168,8 @@ struct InitArgs {
   int noneq;
   int nx, ny, nz;
   size_t n;
+  size_t stride;
+  Placement at;
 };
 
 template <typename S>
@@ -156,6 +178,8 @@ __global__ __launch_bounds__(256) void init_kernel(InitArgs<S> a) {
   const size_t cell = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (cell >= a.n) return;
   const size_t n = a.n;
+  int px, py, pz;
+  node_xyz(cell, a.nx, a.ny, px, py, pz);
   double U[3], b[3], B[3], F[3] = {0, 0, 0}, Sb[3] = {0, 0, 0};
   for (int c = 0; c < 3; ++c) {
     U[c] = a.u[c * n + cell];
@@ -201,7 +225,7 @@ __global__ __launch_bounds__(256) void init_kernel(InitArgs<S> a) {
     v += P[0][0] * h2x * h0y * h0z + P[1][1] * h0x * h2y * h0z + P[2][2] * h0x * h0y * h2z
        + P[0][1] * h1x * h1y * h0z + P[0][2] * h1x * h0y * h1z + P[1][2] * h0x * h1y * h1z;
     v -= 0.5 * (F[0] * h1x * h0y * h0z + F[1] * h0x * h1y * h0z + F[2] * h0x * h0y * h1z);
-    a.F[static_cast<size_t>(i) * n + cell] = E::enc(v, E::fscale(i));
+    a.F[static_cast<size_t>(i) * a.stride + a.at.f(i, px, py, pz)] = E::enc(v, E::fscale(i));
   }
   // magnetic: Hall equilibrium with J = curl b, first-order non-equilibrium, -S/2
   double J[3] = {0, 0, 0};
@@ -222,7 +246,7 @@ __global__ __launch_bounds__(256) void init_kernel(InitArgs<S> a) {
       double v = wm(i) * (b[c] + 4.0 * (xv * B[c] - xb * V[c]));
       if (a.noneq && a.gb) v -= wm(i) * xg / a.omega_b;
       v -= 0.5 * wm(i) * Sb[c];
-      a.G[static_cast<size_t>(i * 3 + c) * n + cell] = E::enc(v, E::mscale(i));
+      a.G[static_cast<size_t>(i * 3 + c) * a.stride + a.at.g(i, px, py, pz)] = E::enc(v, E::mscale(i));
     }
   }
 }
@@ -241,16 +265,20 @@ __global__ __launch_bounds__(256) void get_kernel(View<S> v, Rest r, double* dst
 }
 
 template <typename S>
-__global__ __launch_bounds__(256) void set_kernel(S* F, S* G, size_t n, Rest r, const double* src) {
+__global__ __launch_bounds__(256) void set_kernel(S* F, S* G, size_t n, size_t stride, Placement at, Rest r,
+                                                  const double* src) {
   using E = Enc<S>;
   const size_t cell = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (cell >= n) return;
+  int x, y, z;
+  node_xyz(cell, at.nx, at.ny, x, y, z);
   for (int i = 0; i < kQ; ++i)
-    F[static_cast<size_t>(i) * n + cell] = E::enc(src[static_cast<size_t>(i) * n + cell] - r.f[i], E::fscale(i));
+    F[static_cast<size_t>(i) * stride + at.f(i, x, y, z)] =
+        E::enc(src[static_cast<size_t>(i) * n + cell] - r.f[i], E::fscale(i));
   for (int i = 0; i < 7; ++i)
     for (int c = 0; c < 3; ++c) {
       const size_t k = static_cast<size_t>(i * 3 + c);
-      G[k * n + cell] = E::enc(src[(27 + k) * n + cell] - wm(i) * r.b0[c], E::mscale(i));
+      G[k * stride + at.g(i, x, y, z)] = E::enc(src[(27 + k) * n + cell] - wm(i) * r.b0[c], E::mscale(i));
     }
 }
 
@@ -419,6 +447,11 @@ std::string validate(const flame_params* p) {
   const double cells = static_cast<double>(p->nx) * p->ny * p->nz;
   if (cells >= 1099511627776.0) return "grid too large (nx*ny*nz must be < 2^40)";
   if (p->nz > 65535) return "nz must be <= 65535";
+  // kernels address each population and forcing array with 32-bit byte offsets
+  const double vb = p->storage == FLAME_F64 ? 8.0 : p->storage == FLAME_F32 ? 4.0 : 2.0;
+  const double fb = p->storage == FLAME_F64 ? 8.0 : 4.0;
+  if ((cells + 256.0 + FLAME_STRIDE_PAD_BYTES) * vb > 4294967296.0 || cells * fb > 4294967296.0)
+    return "grid too large: each population / forcing array must fit in 4 GiB";
   if (!(p->nu > 0) || !isfinite(p->nu)) return "nu must be finite and > 0";
   if (!(p->eta > 0) || !isfinite(p->eta)) return "eta must be finite and > 0";
   if (!(p->d_i >= 0) || !isfinite(p->d_i)) return "d_i must be finite and >= 0";
@@ -442,12 +475,13 @@ View<S> make_view(const flame_ctx* c) {
   View<S> v;
   v.F = static_cast<const S*>(s.f_src);
   v.G = static_cast<const S*>(s.g_src);
-  v.f_odd = s.fluid_aa && c->parity == 1;
-  v.g_odd = s.mag_aa && c->parity == 1;
+  v.fmode = s.fluid_aa ? (c->parity == 1 ? 1 : 0) : 2;
+  v.gmode = s.mag_aa ? (c->parity == 1 ? 1 : 0) : 2;
   v.nx = c->p.nx;
   v.ny = c->p.ny;
   v.nz = c->p.nz;
   v.n = c->n;
+  v.stride = c->stride;
   return v;
 }
 
@@ -471,6 +505,17 @@ Rest make_rest(const flame_ctx* c, int32_t deviations) {
   for (int i = 0; i < 27; ++i) r.f[i] = deviations ? 0.0 : c->frest[i];
   for (int i = 0; i < 3; ++i) r.b0[i] = deviations ? 0.0 : c->p.b0[i];
   return r;
+}
+
+Placement make_placement(const flame_ctx* c) {
+  const SetPtrs s = set_ptrs(c);
+  Placement at;
+  at.fpull = !s.fluid_aa;
+  at.gpull = !s.mag_aa;
+  at.nx = c->p.nx;
+  at.ny = c->p.ny;
+  at.nz = c->p.nz;
+  return at;
 }
 
 unsigned blocks_for(size_t n, int threads) { return static_cast<unsigned>((n + threads - 1) / threads); }
@@ -507,7 +552,7 @@ __global__ void max_field_kernel(const double* b, double b0x, double b0y, double
 namespace flame {
 SetPtrs set_ptrs(const flame_ctx* c) {
   const size_t vb = value_bytes(c->p.storage);
-  const size_t n = c->n;
+  const size_t n = c->stride;
   char* base = static_cast<char*>(c->storage);
   SetPtrs s{};
   if (c->p.layout == FLAME_LAYOUT_AB) {
@@ -560,7 +605,7 @@ flame_status flame_rest_populations(const flame_params* p, double* f_rest, doubl
 
 size_t flame_storage_bytes(const flame_params* p) {
   if (!validate(p).empty()) return 0;
-  return values_per_node(*p) * value_bytes(p->storage) * static_cast<size_t>(p->nx) * p->ny * p->nz;
+  return values_per_node(*p) * value_bytes(p->storage) * population_stride(*p);
 }
 
 flame_status flame_init(const flame_params* p, const double* u, const double* b, const double* grad_u,
@@ -582,6 +627,7 @@ flame_status flame_init(const flame_params* p, const double* u, const double* b,
   c->p = *p;
   c->stream = static_cast<hipStream_t>(hip_stream);
   c->n = static_cast<size_t>(p->nx) * p->ny * p->nz;
+  c->stride = population_stride(*p);
   c->storage = storage;
   c->omega = 1.0 / (3.0 * p->nu + 0.5);
   c->omega_b = 1.0 / (4.0 * p->eta + 0.5);
@@ -624,6 +670,8 @@ flame_status flame_init(const flame_params* p, const double* u, const double* b,
     a.ny = p->ny;
     a.nz = p->nz;
     a.n = c->n;
+    a.stride = c->stride;
+    a.at = make_placement(c);
     hipLaunchKernelGGL(init_kernel<S>, dim3(blocks_for(c->n, 256)), dim3(256), 0, c->stream, a);
     return hipGetLastError();
   });
@@ -784,7 +832,8 @@ flame_status flame_set_populations(flame_ctx* c, const double* src, int32_t devi
   hipError_t e = by_storage(c, [&](auto tag) {
     using S = decltype(tag);
     hipLaunchKernelGGL(set_kernel<S>, dim3(blocks_for(c->n, 256)), dim3(256), 0, c->stream,
-                       static_cast<S*>(s.f_src), static_cast<S*>(s.g_src), c->n, make_rest(c, deviations), src);
+                       static_cast<S*>(s.f_src), static_cast<S*>(s.g_src), c->n, c->stride, make_placement(c),
+                       make_rest(c, deviations), src);
     return hipGetLastError();
   });
   if (e != hipSuccess) return fail(c, FLAME_E_HIP, std::string("set kernel: ") + hipGetErrorString(e));

@@ -14,6 +14,7 @@ struct flame_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   size_t n = 0;              // nodes
+  size_t stride = 0;         // elements between consecutive population arrays
   void* storage = nullptr;   // caller-owned populations
   int parity = 0;            // AA in-place sets: 0 = canonical slots, 1 = swapped slots
   int cur = 0;               // two-lattice sets: index of the copy holding the current state
@@ -42,11 +43,23 @@ struct SetPtrs {
   void* f_dst;
   void* g_src;
   void* g_dst;
-  bool fluid_aa;     // fluid set updated in place
-  bool mag_aa;       // magnetic set updated in place
+  bool fluid_aa;     // fluid set updated in place (else two-lattice pull)
+  bool mag_aa;       // magnetic set updated in place (else two-lattice pull)
 };
 
 inline size_t value_bytes(int storage) { return storage == FLAME_F64 ? 8 : storage == FLAME_F32 ? 4 : 2; }
+
+// Population arrays are laid out back to back with a stride of the node count rounded up to
+// 256 bytes plus a pad, so that the 48 arrays do not all start at large powers of two apart.
+#ifndef FLAME_STRIDE_PAD_BYTES
+#define FLAME_STRIDE_PAD_BYTES 0
+#endif
+inline size_t population_stride(const flame_params& p) {
+  const size_t vb = value_bytes(p.storage);
+  const size_t n = static_cast<size_t>(p.nx) * p.ny * p.nz;
+  const size_t align = 256 / vb;
+  return (n + align - 1) / align * align + FLAME_STRIDE_PAD_BYTES / vb;
+}
 inline bool mag_two_lattice(const flame_params& p) {
   return p.layout == FLAME_LAYOUT_AB || p.jmode == FLAME_J_STENCIL;
 }

@@ -1,14 +1,25 @@
-// The fused time-step kernel: load -> moments -> J -> collide (fluid + magnetic) -> stream.
+// The fused time-step kernels: load -> moments -> J -> collide (fluid + magnetic) -> stream.
 //
-// One thread owns one node. Population sets are stored structure-of-arrays,
-// set[q][z][y][x] with x fastest, so a wavefront of 64 threads along x reads and writes
-// contiguous 256-byte (FP32) rows per direction. Streaming is done by the addressing:
-//   two-lattice (push): read own slots of the source copy, write x + c_i of the other copy;
+// Population sets are stored structure-of-arrays, set[q][z][y][x] with x fastest, so a
+// wavefront of 64 threads along x moves contiguous 256-byte (FP32) rows per direction.
+// Streaming is done by the addressing:
+//   two-lattice (pull): read slot i at x - c_i of the source copy, write slot i at x of the
+//     other copy (all stores aligned);
 //   AA in place, even step: read slot i at x, write slot opp(i) at x;
 //   AA in place, odd step:  read slot opp(i) at x - c_i, write slot i at x + c_i.
 // Each AA thread reads and writes exactly the slots it owns, so the in-place update is
 // race-free. With the stencil current the magnetic set is always two-lattice, so the
 // neighbour fields read for curl B are never overwritten during the step.
+//
+// Two kernels:
+//   step_local  - moment-route J: every node independent, one node per thread, 256-wide rows.
+//   step_zmarch - stencil J: a workgroup owns a 64 x 4 tile of (x, y) and marches along z. It
+//     keeps the field fluctuation b of three consecutive planes in LDS (computed once per node
+//     from that node's own magnetic populations, which it holds in registers for the next
+//     iteration) plus, for the current plane, the one-node ring around the tile; J is the
+//     central-difference curl read from LDS.
+
+#include <algorithm>
 
 #include "flame_internal.h"
 
@@ -24,7 +35,9 @@ struct StepArgs {
   const R* force_u;   // [3][n] or null
   const R* force_b;   // [3][n] or null
   int nx, ny, nz;
-  size_t n;
+  int zchunk;         // planes per workgroup (z-marching kernel)
+  size_t n;           // nodes (stride of the caller's forcing arrays)
+  size_t stride;      // elements between consecutive population arrays (n plus padding)
   PhysConst<R> k;
 };
 
@@ -32,124 +45,348 @@ __device__ __forceinline__ size_t node(int x, int y, int z, int nx, int ny) {
   return (static_cast<size_t>(z) * ny + y) * nx + x;
 }
 
-// Field fluctuation b_c at a node from the two-lattice (canonical) magnetic source.
-template <typename S>
-__device__ __forceinline__ typename Enc<S>::R field_at(const StepArgs<S>& a, size_t cell, int comp) {
-  using E = Enc<S>;
-  using R = typename E::R;
-  R s = E::dec(a.g_src[static_cast<size_t>(comp) * a.n + cell], R(1.0 / E::mscale(0)));
+// Addresses: every population array is indexed from a wave-uniform base (set + q * n, held in
+// scalar registers) by a 32-bit per-lane node offset. A thread's nine in-plane neighbour
+// offsets (x + dx, y + dy) are loop invariants; the plane offset z * nx * ny is uniform.
+// The library limits each population array to 4 GiB so byte offsets fit in 32 bits.
+struct Rows {
+  uint32_t r[3][3];   // [dx + 1][dy + 1] -> wrap(y + dy) * nx + wrap(x + dx)
+  __device__ __forceinline__ Rows(int x, int y, int nx, int ny) {
 #pragma unroll
-  for (int i = 1; i < 7; ++i)
-    s += E::dec(a.g_src[static_cast<size_t>(i * 3 + comp) * a.n + cell], R(1.0 / E::mscale(i)));
-  if (a.force_b) s += R(0.5) * a.force_b[static_cast<size_t>(comp) * a.n + cell];
-  return s;
+    for (int dx = -1; dx <= 1; ++dx)
+#pragma unroll
+      for (int dy = -1; dy <= 1; ++dy)
+        r[dx + 1][dy + 1] = static_cast<uint32_t>(wrap(y + dy, ny)) * nx + static_cast<uint32_t>(wrap(x + dx, nx));
+  }
+  __device__ __forceinline__ uint32_t at(int dx, int dy) const { return r[dx + 1][dy + 1]; }
+};
+
+template <typename S>
+__device__ __forceinline__ S ld(const S* base, uint32_t off) {
+  return *reinterpret_cast<const S*>(reinterpret_cast<const char*>(base) + off * static_cast<uint32_t>(sizeof(S)));
+}
+#ifndef FLAME_NT_STORES
+#define FLAME_NT_STORES 1
+#endif
+template <typename S>
+__device__ __forceinline__ void st(S* base, uint32_t off, S v) {
+  S* p = reinterpret_cast<S*>(reinterpret_cast<char*>(base) + off * static_cast<uint32_t>(sizeof(S)));
+  if (FLAME_NT_STORES)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
 }
 
-// JM: 0 moment route, 1 stencil. FAA / MAA: fluid / magnetic set in place. PAR: AA parity.
-template <typename S, int JM, bool FAA, bool MAA, int PAR>
-__global__ __launch_bounds__(256) void step_kernel(StepArgs<S> a) {
+// Plane offsets of z - 1, z, z + 1 (periodic), uniform across the workgroup.
+struct Planes {
+  uint32_t p[3];
+  __device__ __forceinline__ Planes(int z, int nz, uint32_t plane) {
+    p[0] = static_cast<uint32_t>(wrap(z - 1, nz)) * plane;
+    p[1] = static_cast<uint32_t>(z) * plane;
+    p[2] = static_cast<uint32_t>(wrap(z + 1, nz)) * plane;
+  }
+  __device__ __forceinline__ uint32_t at(int dz) const { return p[dz + 1]; }
+};
+
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2): hardware
+// workgroup h runs on XCD h % 8. Remap so that XCD j processes one contiguous range of logical
+// tiles (x fastest, then y, then z): neighbouring tiles, which share halo rows and the cache
+// lines that shifted stores straddle, then sit behind the same L2.
+#ifndef FLAME_XCD_REMAP
+#define FLAME_XCD_REMAP 1
+#endif
+constexpr unsigned kXCDs = 8;
+
+__device__ __forceinline__ void logical_block(unsigned gx, unsigned gy, unsigned gz, unsigned& bx, unsigned& by,
+                                              unsigned& bz) {
+  const unsigned total = gx * gy * gz;
+  const unsigned h = blockIdx.x;
+  unsigned l = h;
+  if (FLAME_XCD_REMAP) {
+    const unsigned q = total / kXCDs, r = total % kXCDs;
+    const unsigned j = h % kXCDs, k = h / kXCDs;
+    l = j * q + min(j, r) + k;
+  }
+  bx = l % gx;
+  by = (l / gx) % gy;
+  bz = l / (gx * gy);
+}
+
+// Fluid populations of the node. FAA: in place (PAR selects the AA step); else pull.
+template <typename S, bool FAA, int PAR>
+__device__ __forceinline__ void load_fluid(const StepArgs<S>& a, const Rows& rw, const Planes& pl,
+                                           typename Enc<S>::R (&f)[kQ]) {
   using E = Enc<S>;
   using R = typename E::R;
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int y = blockIdx.y * blockDim.y + threadIdx.y;
-  const int z = blockIdx.z;
-  if (x >= a.nx || y >= a.ny) return;
-  const int nx = a.nx, ny = a.ny, nz = a.nz;
-  const size_t n = a.n;
-  const size_t cell = node(x, y, z, nx, ny);
-
-  R f[kQ], g[kM];
 #pragma unroll
   for (int i = 0; i < kQ; ++i) {
-    size_t src;
-    if (FAA && PAR == 1)
-      src = static_cast<size_t>(oppq(i)) * n +
-            node(wrap(x - cq(i, 0), nx), wrap(y - cq(i, 1), ny), wrap(z - cq(i, 2), nz), nx, ny);
-    else
-      src = static_cast<size_t>(i) * n + cell;
-    f[i] = E::dec(a.f_src[src], R(1.0 / E::fscale(i)));
+    const bool own = FAA && PAR == 0;
+    const uint32_t off = own ? rw.at(0, 0) + pl.at(0) : rw.at(-cq(i, 0), -cq(i, 1)) + pl.at(-cq(i, 2));
+    const S* base = a.f_src + static_cast<size_t>(FAA && PAR == 1 ? oppq(i) : i) * a.stride;
+    f[i] = E::dec(ld(base, off), R(1.0 / E::fscale(i)));
   }
+}
+
+template <typename S, bool FAA, int PAR>
+__device__ __forceinline__ void store_fluid(const StepArgs<S>& a, const Rows& rw, const Planes& pl,
+                                            const typename Enc<S>::R (&f)[kQ]) {
+  using E = Enc<S>;
+  using R = typename E::R;
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) {
+    const bool shifted = FAA && PAR == 1;
+    const uint32_t off = shifted ? rw.at(cq(i, 0), cq(i, 1)) + pl.at(cq(i, 2)) : rw.at(0, 0) + pl.at(0);
+    S* base = a.f_dst + static_cast<size_t>(FAA && PAR == 0 ? oppq(i) : i) * a.stride;
+    st(base, off, E::enc(f[i], R(E::fscale(i))));
+  }
+}
+
+template <typename S, bool MAA, int PAR>
+__device__ __forceinline__ void load_magnetic(const StepArgs<S>& a, const Rows& rw, const Planes& pl,
+                                              typename Enc<S>::R (&g)[kM]) {
+  using E = Enc<S>;
+  using R = typename E::R;
 #pragma unroll
   for (int i = 0; i < 7; ++i) {
+    const bool own = MAA && PAR == 0;
+    const uint32_t off = own ? rw.at(0, 0) + pl.at(0) : rw.at(-xim(i, 0), -xim(i, 1)) + pl.at(-xim(i, 2));
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      size_t src;
-      if (MAA && PAR == 1)
-        src = static_cast<size_t>(oppm(i) * 3 + c) * n +
-              node(wrap(x - xim(i, 0), nx), wrap(y - xim(i, 1), ny), wrap(z - xim(i, 2), nz), nx, ny);
-      else
-        src = static_cast<size_t>(i * 3 + c) * n + cell;
-      g[i * 3 + c] = E::dec(a.g_src[src], R(1.0 / E::mscale(i)));
+      const S* base = a.g_src + static_cast<size_t>((MAA && PAR == 1 ? oppm(i) : i) * 3 + c) * a.stride;
+      g[i * 3 + c] = E::dec(ld(base, off), R(1.0 / E::mscale(i)));
     }
   }
+}
 
-  // moments
-  const FluidMoments<R> m = fluid_moments(f);
-  R F[3] = {R(0), R(0), R(0)}, Sb[3] = {R(0), R(0), R(0)};
-  if (a.force_u) {
+template <typename S, bool MAA, int PAR>
+__device__ __forceinline__ void store_magnetic(const StepArgs<S>& a, const Rows& rw, const Planes& pl,
+                                               const typename Enc<S>::R (&g)[kM]) {
+  using E = Enc<S>;
+  using R = typename E::R;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) F[c] = a.force_u[static_cast<size_t>(c) * n + cell];
-  }
-  if (a.force_b) {
+  for (int i = 0; i < 7; ++i) {
+    const bool shifted = MAA && PAR == 1;
+    const uint32_t off = shifted ? rw.at(xim(i, 0), xim(i, 1)) + pl.at(xim(i, 2)) : rw.at(0, 0) + pl.at(0);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) Sb[c] = a.force_b[static_cast<size_t>(c) * n + cell];
+    for (int c = 0; c < 3; ++c) {
+      S* base = a.g_dst + static_cast<size_t>((MAA && PAR == 0 ? oppm(i) : i) * 3 + c) * a.stride;
+      st(base, off, E::enc(g[i * 3 + c], R(E::mscale(i))));
+    }
   }
+}
+
+// Field fluctuation component c of a node from its magnetic populations, with the source
+// half-shift; one fixed summation order everywhere so a node's b is bitwise the same
+// whichever thread computes it.
+template <typename R>
+__device__ __forceinline__ R b_component(const R (&g)[kM], int c, R half_src) {
+  R s = g[c];
+#pragma unroll
+  for (int i = 1; i < 7; ++i) s += g[i * 3 + c];
+  return s + half_src;
+}
+
+template <typename S>
+__device__ __forceinline__ void forcing_at(const StepArgs<S>& a, uint32_t cell, typename Enc<S>::R (&F)[3],
+                                           typename Enc<S>::R (&Sb)[3]) {
+  using R = typename Enc<S>::R;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    F[c] = a.force_u ? ld(a.force_u + static_cast<size_t>(c) * a.n, cell) : R(0);
+    Sb[c] = a.force_b ? ld(a.force_b + static_cast<size_t>(c) * a.n, cell) : R(0);
+  }
+}
+
+// Node update from loaded populations and J: moments, both collisions, in place in f and g.
+template <typename R>
+__device__ __forceinline__ void collide_node(R (&f)[kQ], R (&g)[kM], const FluidMoments<R>& m, const R (&U)[3],
+                                             const R (&b)[3], const R (&J)[3], const R (&F)[3], const R (&Sb)[3],
+                                             const PhysConst<R>& k) {
   const R rho = R(1) + m.drho;
-  const R inv_rho = R(1) / rho;
+  const R b0[3] = {k.b0[0], k.b0[1], k.b0[2]};
+  const R B[3] = {b0[0] + b[0], b0[1] + b[1], b0[2] + b[2]};
+  collide_fluid(f, m, rho, U, b, b0, F, k.omega);
+  collide_magnetic(g, U, B, b, J, Sb, k.alpha, k.omega_b);
+}
+
+// ------------------------------------------------------------------ moment-route kernel
+constexpr int kLocalThreads = 256;
+
+template <typename S, bool FAA, bool MAA, int PAR>
+__global__ __launch_bounds__(kLocalThreads) void step_local(StepArgs<S> a) {
+  using R = typename Enc<S>::R;
+  unsigned bx, by, bz;
+  logical_block((a.nx + kLocalThreads - 1) / kLocalThreads, a.ny, a.nz, bx, by, bz);
+  const int x = bx * kLocalThreads + threadIdx.x;
+  const int y = by;
+  const int z = bz;
+  if (x >= a.nx) return;
+  const Rows rw(x, y, a.nx, a.ny);
+  const Planes pl(z, a.nz, static_cast<uint32_t>(a.nx) * a.ny);
+  const uint32_t cell = rw.at(0, 0) + pl.at(0);
+  R f[kQ], g[kM];
+  load_fluid<S, FAA, PAR>(a, rw, pl, f);
+  load_magnetic<S, MAA, PAR>(a, rw, pl, g);
+  R F[3], Sb[3];
+  forcing_at(a, cell, F, Sb);
+  const FluidMoments<R> m = fluid_moments(f);
+  const R inv_rho = R(1) / (R(1) + m.drho);
   const R U[3] = {(m.jx + R(0.5) * F[0]) * inv_rho, (m.jy + R(0.5) * F[1]) * inv_rho,
                   (m.jz + R(0.5) * F[2]) * inv_rho};
   R b[3], lam[3][3];
   magnetic_moments(g, b, lam);
 #pragma unroll
-  for (int c = 0; c < 3; ++c) b[c] += R(0.5) * Sb[c];
+  for (int c = 0; c < 3; ++c) b[c] = b_component(g, c, R(0.5) * Sb[c]);
   const R B[3] = {a.k.b0[0] + b[0], a.k.b0[1] + b[1], a.k.b0[2] + b[2]};
-
-  // current density
   R J[3];
-  if (JM == 0) {
-    current_from_moments(lam, U, B, a.k.alpha, a.k.omega_b, J);
-  } else {
-    const int xp = wrap(x + 1, nx), xm = wrap(x - 1, nx);
-    const int yp = wrap(y + 1, ny), ym = wrap(y - 1, ny);
-    const int zp = wrap(z + 1, nz), zm = wrap(z - 1, nz);
-    const R bz_yp = field_at(a, node(x, yp, z, nx, ny), 2), bz_ym = field_at(a, node(x, ym, z, nx, ny), 2);
-    const R by_zp = field_at(a, node(x, y, zp, nx, ny), 1), by_zm = field_at(a, node(x, y, zm, nx, ny), 1);
-    const R bx_zp = field_at(a, node(x, y, zp, nx, ny), 0), bx_zm = field_at(a, node(x, y, zm, nx, ny), 0);
-    const R bz_xp = field_at(a, node(xp, y, z, nx, ny), 2), bz_xm = field_at(a, node(xm, y, z, nx, ny), 2);
-    const R by_xp = field_at(a, node(xp, y, z, nx, ny), 1), by_xm = field_at(a, node(xm, y, z, nx, ny), 1);
-    const R bx_yp = field_at(a, node(x, yp, z, nx, ny), 0), bx_ym = field_at(a, node(x, ym, z, nx, ny), 0);
-    J[0] = R(0.5) * (bz_yp - bz_ym) - R(0.5) * (by_zp - by_zm);
-    J[1] = R(0.5) * (bx_zp - bx_zm) - R(0.5) * (bz_xp - bz_xm);
-    J[2] = R(0.5) * (by_xp - by_xm) - R(0.5) * (bx_yp - bx_ym);
-  }
+  current_from_moments(lam, U, B, a.k.alpha, a.k.omega_b, J);
+  collide_node(f, g, m, U, b, J, F, Sb, a.k);
+  store_fluid<S, FAA, PAR>(a, rw, pl, f);
+  store_magnetic<S, MAA, PAR>(a, rw, pl, g);
+}
 
-  const R b0[3] = {a.k.b0[0], a.k.b0[1], a.k.b0[2]};
-  collide_fluid(f, m, rho, U, b, b0, F, a.k.omega);
-  collide_magnetic(g, U, B, b, J, Sb, a.k.alpha, a.k.omega_b);
+// ------------------------------------------------------------------ stencil-route kernel
+// Tile and z-chunk of the stencil kernel (tuning parameters, overridable at build time).
+#ifndef FLAME_TY
+#define FLAME_TY 4        // FP32 / FP16 storage
+#endif
+#ifndef FLAME_TY64
+#define FLAME_TY64 4      // FP64 storage (twice the registers per node)
+#endif
+#ifndef FLAME_ZCHUNK
+#define FLAME_ZCHUNK 32
+#endif
+#ifndef FLAME_ZMARCH_WAVES_PER_EU
+#define FLAME_ZMARCH_WAVES_PER_EU 1
+#endif
+constexpr int kTX = 64;
+template <typename R>
+struct Tile {
+  static constexpr int ty = sizeof(R) == 8 ? FLAME_TY64 : FLAME_TY;
+};
+constexpr int kZChunk = FLAME_ZCHUNK;   // planes per workgroup
 
-  // stream + store
+template <typename S, bool FAA, int PAR>
+__global__ __launch_bounds__(kTX * Tile<typename Enc<S>::R>::ty, FLAME_ZMARCH_WAVES_PER_EU) void step_zmarch(
+    StepArgs<S> a) {
+  using E = Enc<S>;
+  using R = typename E::R;
+  constexpr int kTY = Tile<R>::ty;
+  // b of the tile plus its one-node ring for a rolling window of planes:
+  // [plane slot][ly + 1][lx + 1][component]. Four slots: a slot is rewritten two iterations
+  // after it was last read, so one barrier per plane separates every write from every read.
+  __shared__ R sb[4][kTY + 2][kTX + 2][3];
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  unsigned bx, by, bz;
+  logical_block((nx + kTX - 1) / kTX, (ny + kTY - 1) / kTY, (nz + a.zchunk - 1) / a.zchunk, bx, by, bz);
+  const int x0 = bx * kTX, y0 = by * kTY;
+  const int w = min(kTX, nx - x0), h = min(kTY, ny - y0);
+  const int z_begin = bz * a.zchunk;
+  const int z_end = min(nz, z_begin + a.zchunk);
+  const int lx = threadIdx.x, ly = threadIdx.y;
+  const int tid = ly * kTX + lx;
+  const bool active = lx < w && ly < h;
+  const int x = x0 + lx, y = y0 + ly;
+
+  const uint32_t plane = static_cast<uint32_t>(nx) * ny;
+  const Rows rw(active ? x : 0, active ? y : 0, nx, ny);
+  auto half_src = [&](uint32_t cell, int c) -> R {
+    return a.force_b ? R(0.5) * ld(a.force_b + static_cast<size_t>(c) * a.n, cell) : R(0);
+  };
+  auto put_b = [&](int slot, const R (&g)[kM], uint32_t cell) {
 #pragma unroll
-  for (int i = 0; i < kQ; ++i) {
-    size_t dst;
-    if (FAA && PAR == 0)
-      dst = static_cast<size_t>(oppq(i)) * n + cell;
-    else
-      dst = static_cast<size_t>(i) * n +
-            node(wrap(x + cq(i, 0), nx), wrap(y + cq(i, 1), ny), wrap(z + cq(i, 2), nz), nx, ny);
-    a.f_dst[dst] = E::enc(f[i], R(E::fscale(i)));
-  }
+    for (int c = 0; c < 3; ++c) sb[slot][ly + 1][lx + 1][c] = b_component(g, c, half_src(cell, c));
+  };
+  // ring nodes of the current plane: two components of b from their seven pulled populations
+  auto ring = [&](int slot, const Planes& pl) {
+    for (int task = tid; task < 2 * w + 2 * h; task += kTX * kTY) {
+      int rx, ry, c0, c1;
+      if (task < 2 * w) {
+        rx = task < w ? task : task - w;
+        ry = task < w ? -1 : h;
+        c0 = 0; c1 = 2;                       // y-neighbours enter through B_x and B_z
+      } else {
+        const int t = task - 2 * w;
+        ry = t < h ? t : t - h;
+        rx = t < h ? -1 : w;
+        c0 = 1; c1 = 2;                       // x-neighbours enter through B_y and B_z
+      }
+      const Rows rr(wrap(x0 + rx, nx), wrap(y0 + ry, ny), nx, ny);
+      // same summation order as b_component
+      R s0 = R(0), s1 = R(0);
 #pragma unroll
-  for (int i = 0; i < 7; ++i) {
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      size_t dst;
-      if (MAA && PAR == 0)
-        dst = static_cast<size_t>(oppm(i) * 3 + c) * n + cell;
-      else
-        dst = static_cast<size_t>(i * 3 + c) * n +
-              node(wrap(x + xim(i, 0), nx), wrap(y + xim(i, 1), ny), wrap(z + xim(i, 2), nz), nx, ny);
-      a.g_dst[dst] = E::enc(g[i * 3 + c], R(E::mscale(i)));
+      for (int i = 0; i < 7; ++i) {
+        const uint32_t off = rr.at(-xim(i, 0), -xim(i, 1)) + pl.at(-xim(i, 2));
+        const R v0 = E::dec(ld(a.g_src + static_cast<size_t>(i * 3 + c0) * a.stride, off), R(1.0 / E::mscale(i)));
+        const R v1 = E::dec(ld(a.g_src + static_cast<size_t>(i * 3 + c1) * a.stride, off), R(1.0 / E::mscale(i)));
+        s0 = i == 0 ? v0 : s0 + v0;
+        s1 = i == 0 ? v1 : s1 + v1;
+      }
+      const uint32_t cell = rr.at(0, 0) + pl.at(0);
+      sb[slot][ry + 1][rx + 1][c0] = s0 + half_src(cell, c0);
+      sb[slot][ry + 1][rx + 1][c1] = s1 + half_src(cell, c1);
     }
+  };
+
+  R g_next[kM];
+  if (active) {
+    R gp[kM];
+    const Planes pp(wrap(z_begin - 1, nz), nz, plane);
+    load_magnetic<S, false, 0>(a, rw, pp, gp);
+    put_b(0, gp, rw.at(0, 0) + pp.at(0));
+    const Planes p0(z_begin, nz, plane);
+    load_magnetic<S, false, 0>(a, rw, p0, g_next);
+    put_b(1, g_next, rw.at(0, 0) + p0.at(0));
+  }
+  int prev = 0, cur = 1, next = 2, spare = 3;
+  for (int z = z_begin; z < z_end; ++z) {
+    R g[kM];
+#pragma unroll
+    for (int q = 0; q < kM; ++q) g[q] = g_next[q];
+    const Planes pl(z, nz, plane);
+    const Planes pn(wrap(z + 1, nz), nz, plane);
+    const uint32_t cell = rw.at(0, 0) + pl.at(0);
+    R U[3], b[3], F[3], Sb[3];
+    if (active) {
+      load_magnetic<S, false, 0>(a, rw, pn, g_next);
+      put_b(next, g_next, rw.at(0, 0) + pn.at(0));
+    }
+    ring(cur, pl);
+    if (active) {
+      // the fluid half of the update needs no J: collide and store it before the barrier
+      R f[kQ];
+      load_fluid<S, FAA, PAR>(a, rw, pl, f);
+      forcing_at(a, cell, F, Sb);
+      const FluidMoments<R> m = fluid_moments(f);
+      const R inv_rho = R(1) / (R(1) + m.drho);
+      U[0] = (m.jx + R(0.5) * F[0]) * inv_rho;
+      U[1] = (m.jy + R(0.5) * F[1]) * inv_rho;
+      U[2] = (m.jz + R(0.5) * F[2]) * inv_rho;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) b[c] = b_component(g, c, R(0.5) * Sb[c]);
+      const R b0[3] = {a.k.b0[0], a.k.b0[1], a.k.b0[2]};
+      collide_fluid(f, m, R(1) + m.drho, U, b, b0, F, a.k.omega);
+      store_fluid<S, FAA, PAR>(a, rw, pl, f);
+    }
+    __syncthreads();
+    if (active) {
+      const R(&P)[kTY + 2][kTX + 2][3] = sb[prev];
+      const R(&C)[kTY + 2][kTX + 2][3] = sb[cur];
+      const R(&N)[kTY + 2][kTX + 2][3] = sb[next];
+      const int px = lx + 1, py = ly + 1;
+      R J[3];
+      J[0] = R(0.5) * (C[py + 1][px][2] - C[py - 1][px][2]) - R(0.5) * (N[py][px][1] - P[py][px][1]);
+      J[1] = R(0.5) * (N[py][px][0] - P[py][px][0]) - R(0.5) * (C[py][px + 1][2] - C[py][px - 1][2]);
+      J[2] = R(0.5) * (C[py][px + 1][1] - C[py][px - 1][1]) - R(0.5) * (C[py + 1][px][0] - C[py - 1][px][0]);
+      const R B[3] = {a.k.b0[0] + b[0], a.k.b0[1] + b[1], a.k.b0[2] + b[2]};
+      collide_magnetic(g, U, B, b, J, Sb, a.k.alpha, a.k.omega_b);
+      store_magnetic<S, false, 0>(a, rw, pl, g);
+    }
+    const int t = prev;
+    prev = cur;
+    cur = next;
+    next = spare;
+    spare = t;
   }
 }
 
@@ -167,27 +404,34 @@ static hipError_t launch_typed(const flame_ctx* c, const SetPtrs& s) {
   a.ny = c->p.ny;
   a.nz = c->p.nz;
   a.n = c->n;
+  a.stride = c->stride;
   a.k.omega = R(c->omega);
   a.k.omega_b = R(c->omega_b);
   a.k.alpha = R(c->p.d_i);
   for (int i = 0; i < 3; ++i) a.k.b0[i] = R(c->p.b0[i]);
-  const dim3 block(64, 4, 1);
-  const dim3 grid((c->p.nx + 63) / 64, (c->p.ny + 3) / 4, c->p.nz);
-  const bool st = c->p.jmode == FLAME_J_STENCIL;
   const int par = c->parity;
-#define FLAME_LAUNCH(JM, FAA, MAA, PAR) \
-  hipLaunchKernelGGL((step_kernel<S, JM, FAA, MAA, PAR>), grid, block, 0, c->stream, a)
-  if (!s.fluid_aa) {
-    if (st) FLAME_LAUNCH(1, false, false, 0);
-    else FLAME_LAUNCH(0, false, false, 0);
-  } else if (st) {
-    if (par == 0) FLAME_LAUNCH(1, true, false, 0);
-    else FLAME_LAUNCH(1, true, false, 1);
+  if (c->p.jmode == FLAME_J_STENCIL) {
+    constexpr int kTY = Tile<R>::ty;
+    a.zchunk = std::min(c->p.nz, kZChunk);
+    const dim3 block(kTX, kTY, 1);
+    const dim3 grid(((c->p.nx + kTX - 1) / kTX) * ((c->p.ny + kTY - 1) / kTY) * ((c->p.nz + a.zchunk - 1) / a.zchunk));
+    if (!s.fluid_aa)
+      hipLaunchKernelGGL((step_zmarch<S, false, 0>), grid, block, 0, c->stream, a);
+    else if (par == 0)
+      hipLaunchKernelGGL((step_zmarch<S, true, 0>), grid, block, 0, c->stream, a);
+    else
+      hipLaunchKernelGGL((step_zmarch<S, true, 1>), grid, block, 0, c->stream, a);
   } else {
-    if (par == 0) FLAME_LAUNCH(0, true, true, 0);
-    else FLAME_LAUNCH(0, true, true, 1);
+    a.zchunk = 1;
+    const dim3 block(kLocalThreads, 1, 1);
+    const dim3 grid(((c->p.nx + kLocalThreads - 1) / kLocalThreads) * c->p.ny * c->p.nz);
+    if (!s.fluid_aa)
+      hipLaunchKernelGGL((step_local<S, false, false, 0>), grid, block, 0, c->stream, a);
+    else if (par == 0)
+      hipLaunchKernelGGL((step_local<S, true, true, 0>), grid, block, 0, c->stream, a);
+    else
+      hipLaunchKernelGGL((step_local<S, true, true, 1>), grid, block, 0, c->stream, a);
   }
-#undef FLAME_LAUNCH
   return hipGetLastError();
 }
 
