@@ -29,6 +29,19 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0        # MI355X HBM3E peak
+
+# HBM traffic of the headline kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE passes, calibrated on
+# a plain copy (profiles/traffic_step_f32_stencil_512.md). Valid only for the kernel source it was
+# measured on: reported as null once the fingerprint of the kernel sources changes.
+TRAFFIC_RECORD = {"fingerprint": "e682d944b83d657d", "GB_per_launch": 69.03,
+                  "profile": "profiles/traffic_step_f32_stencil_512.md"}
+
+
+def kernel_fingerprint():
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2212_11024_amd", "csrc")
+    data = b"".join(open(os.path.join(csrc, f), "rb").read() for f in ("flame_step.hip", "flame_device.h"))
+    return hashlib.sha256(data).hexdigest()[:16]
 WORKLOAD = "forced Hall-MHD turbulence 512^3 (FP32 deviation storage, FP64 reductions)"
 
 
@@ -94,6 +107,26 @@ def time_variant(n, storage, jmode, steps, warmup, fields):
     }
 
 
+def copy_probe(gib=4, reps=5):
+    """Plain device-to-device copy of a known size: achievable read+write bandwidth."""
+    import torch
+    n = gib * (1 << 30) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return {"bytes_each_way": gib * (1 << 30), "ms": round(ms, 4), "GBps": round(2 * gib * (1 << 30) / (ms * 1e6), 1)}
+
+
 def cpu_baseline(seconds=15.0):
     """The FP64 oracle (closed-form route, as it stands) on a 32^3 sample of the workload's
     physics, on the host cores; MLUPS = nodes x steps / time."""
@@ -127,6 +160,8 @@ def main(argv=None):
     ap.add_argument("--variants", default="all", help="all | headline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also time a plain 4 GiB device copy (bandwidth reference and counter calibration)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU slab "
@@ -140,6 +175,7 @@ def main(argv=None):
         build()
     torch.cuda.set_device(0)
     n = args.size
+    copy = copy_probe() if args.copy_probe else None
     fields = workload_fields(n, "cuda")
     torch.cuda.synchronize()
     variants = [("f32", "stencil")]
@@ -156,6 +192,9 @@ def main(argv=None):
     del fields
     torch.cuda.empty_cache()
     head = results[0]
+    traffic = None
+    if n == 512 and kernel_fingerprint() == TRAFFIC_RECORD["fingerprint"]:
+        traffic = TRAFFIC_RECORD["GB_per_launch"]
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
@@ -178,10 +217,13 @@ def main(argv=None):
                    "j_mode": "stencil", "layout": "aa (fluid in place, magnetic double-buffered)",
                    "forcing": "static, |k| <= 2, rms 1e-5"},
         "roofline": {"bound": "hbm", "achieved": round(head["achieved_GBps"], 1), "peak": HBM_PEAK_GBPS,
-                     "unit": "GB/s", "frac": round(head["achieved_GBps"] / HBM_PEAK_GBPS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(head["achieved_GBps"] / HBM_PEAK_GBPS, 4),
+                     "traffic": traffic, "traffic_unit": "GB per launch (measured HBM bytes)",
+                     "algorithmic_GB_per_launch": round(head["bytes_per_node"] * n ** 3 / 1e9, 3),
                      "bytes_per_node": head["bytes_per_node"]},
         "variants": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()} for r in results],
         "adjoint_forward_ratio": None,
+        "copy_probe": copy,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
