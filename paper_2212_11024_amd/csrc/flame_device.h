@@ -10,6 +10,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// Per-node arithmetic is host-and-device so the same code can be exercised on the CPU.
+#define FLAME_HD __host__ __device__ __forceinline__
+
 namespace flame {
 
 // ------------------------------------------------------------------ lattice tables
@@ -100,7 +103,7 @@ struct FluidMoments {
 };
 
 template <typename R>
-__device__ __forceinline__ FluidMoments<R> fluid_moments(const R (&f)[kQ]) {
+FLAME_HD FluidMoments<R> fluid_moments(const R (&f)[kQ]) {
   FluidMoments<R> m{};
 #pragma unroll
   for (int i = 0; i < kQ; ++i) {
@@ -122,7 +125,7 @@ __device__ __forceinline__ FluidMoments<R> fluid_moments(const R (&f)[kQ]) {
 // Field fluctuation b = sum dg (the rest part sums to b0) and Lambda_ab = sum_i xi_ia g_ib,
 // which for D3Q7 is the difference of the +a and -a populations (the rest part cancels).
 template <typename R>
-__device__ __forceinline__ void magnetic_moments(const R (&g)[kM], R (&b)[3], R (&lam)[3][3]) {
+FLAME_HD void magnetic_moments(const R (&g)[kM], R (&b)[3], R (&lam)[3][3]) {
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     R s = g[a];
@@ -140,7 +143,7 @@ __device__ __forceinline__ void magnetic_moments(const R (&g)[kM], R (&b)[3], R 
 // M(B) J = J x B, J0 = eps:Lambda - 2 U x B. Written as J + k (J x B) = r, whose solution is
 // J = (r - k r x B + k^2 (r . B) B) / (1 + k^2 |B|^2), with k = 8 alpha w_B and r = -4 w_B J0.
 template <typename R>
-__device__ __forceinline__ void current_from_moments(const R (&lam)[3][3], const R (&U)[3],
+FLAME_HD void current_from_moments(const R (&lam)[3][3], const R (&U)[3],
                                                      const R (&B)[3], R alpha, R omega_b,
                                                      R (&J)[3]) {
   const R j0x = lam[1][2] - lam[2][1] - R(2) * (U[1] * B[2] - U[2] * B[1]);
@@ -165,7 +168,7 @@ __device__ __forceinline__ void current_from_moments(const R (&lam)[3][3], const
 template <typename R>
 struct Axis {
   R e[3], h0[3], h1[3], h2[3];
-  __device__ __forceinline__ explicit Axis(R u) {
+  FLAME_HD explicit Axis(R u) {
     const R u2 = u * u;
     e[0] = R(3) * (u2 - u); e[1] = R(-1.5) * u2; e[2] = R(3) * (u2 + u);
     h0[0] = R(0.5) * (u2 - u); h0[1] = R(1) - u2; h0[2] = R(0.5) * (u2 + u);
@@ -184,7 +187,7 @@ struct Axis {
 // In deviations: f^mhd(0)_i - f_rest_i = w_i [d rho E_i + (E_i - 1)] + (w_i / 2 c_s^4)
 // (M(B) - M(b0)) : (c c - c_s^2 I), E_i = prod_a (1 + e_a), M(B) = |B|^2/2 I - B B.
 template <typename R>
-__device__ __forceinline__ void collide_fluid(R (&f)[kQ], const FluidMoments<R>& m, R rho,
+FLAME_HD void collide_fluid(R (&f)[kQ], const FluidMoments<R>& m, R rho,
                                               const R (&U)[3], const R (&b)[3], const R (&b0)[3],
                                               const R (&F)[3], R omega) {
   // deviatoric K = S2 - rho U U + (U F + F U)/2 + (B B - b0 b0); B B - b0 b0 = b0 b + b b0 + b b
@@ -230,7 +233,7 @@ __device__ __forceinline__ void collide_fluid(R (&f)[kQ], const FluidMoments<R>&
 // gHall_eq): g* = g - w_B (g - g^Hall(0)) + (1 - w_B/2) W_i S. With V = U - alpha J and
 // E_ac = V_a B_c - B_a V_c, g^Hall(0)_{+-a, c} = W (B_c +- 4 E_ac), g^Hall(0)_{0, c} = W_0 B_c.
 template <typename R>
-__device__ __forceinline__ void collide_magnetic(R (&g)[kM], const R (&U)[3], const R (&B)[3],
+FLAME_HD void collide_magnetic(R (&g)[kM], const R (&U)[3], const R (&B)[3],
                                                  const R (&b)[3], const R (&J)[3],
                                                  const R (&S)[3], R alpha, R omega_b) {
   const R V[3] = {U[0] - alpha * J[0], U[1] - alpha * J[1], U[2] - alpha * J[2]};
@@ -251,7 +254,224 @@ __device__ __forceinline__ void collide_magnetic(R (&g)[kM], const R (&U)[3], co
   }
 }
 
+// ------------------------------------------------------------------ per-node reverse pass
+// Derivatives of the 1-D factors of Axis with respect to u (h2 is constant).
+template <typename R>
+struct AxisD {
+  R de[3], dh0[3], dh1[3];
+  FLAME_HD explicit AxisD(R u) {
+    de[0] = R(6) * u - R(3); de[1] = R(-3) * u; de[2] = R(6) * u + R(3);
+    dh0[0] = u - R(0.5); dh0[1] = R(-2) * u; dh0[2] = u + R(0.5);
+    dh1[0] = R(1); dh1[1] = R(-2); dh1[2] = R(1);
+  }
+};
+
+// Vector-Jacobian product of one node's collision (the adjoint of collide_fluid +
+// collide_magnetic with the moments and, on the moment route, J recomputed from the node's
+// pre-collision deviations f, g). Given mf, mg = d loss / d(post-collision deviations), returns
+// lf, lg = d loss / d(pre-collision deviations) through this node's collision, and lJ =
+// d loss / dJ (stencil route: J is an input computed from neighbouring fields, Jst; on the moment
+// route lJ is folded into lf, lg and returned as zero). F, S: forcing at the node.
+template <typename R, bool MOMENT>
+FLAME_HD void collide_vjp(const R (&f)[kQ], const R (&g)[kM], const R (&F)[3], const R (&S)[3],
+                          const R (&Jst)[3], const PhysConst<R>& k, const R (&mf)[kQ], const R (&mg)[kM],
+                          R (&lf)[kQ], R (&lg)[kM], R (&lJ)[3]) {
+  // ---- forward recomputation
+  const FluidMoments<R> m = fluid_moments(f);
+  const R rho = R(1) + m.drho;
+  const R inv_rho = R(1) / rho;
+  const R U[3] = {(m.jx + R(0.5) * F[0]) * inv_rho, (m.jy + R(0.5) * F[1]) * inv_rho,
+                  (m.jz + R(0.5) * F[2]) * inv_rho};
+  R b[3], lam[3][3];
+  magnetic_moments(g, b, lam);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) b[c] += R(0.5) * S[c];
+  const R b0[3] = {k.b0[0], k.b0[1], k.b0[2]};
+  const R B[3] = {b0[0] + b[0], b0[1] + b[1], b0[2] + b[2]};
+  R J[3];
+  if (MOMENT) current_from_moments(lam, U, B, k.alpha, k.omega_b, J);
+  else { J[0] = Jst[0]; J[1] = Jst[1]; J[2] = Jst[2]; }
+  const R V[3] = {U[0] - k.alpha * J[0], U[1] - k.alpha * J[1], U[2] - k.alpha * J[2]};
+
+  R lU[3] = {R(0), R(0), R(0)}, lb[3] = {R(0), R(0), R(0)}, lB[3] = {R(0), R(0), R(0)};
+  R lrho = R(0);
+  R llam[3][3] = {};
+
+  // ---- magnetic: g* = (1 - w_B) g + w_B g^Hall(0)(b, E) + source
+  {
+    const R ob = k.omega_b;
+#pragma unroll
+    for (int q = 0; q < kM; ++q) lg[q] = (R(1) - ob) * mg[q];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      R acc = R(0.25) * ob * mg[c];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) acc += R(0.125) * ob * (mg[(4 + a) * 3 + c] + mg[(1 + a) * 3 + c]);
+      lb[c] += acc;
+    }
+    R lV[3] = {R(0), R(0), R(0)};
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        if (a == c) continue;
+        // g^Hall(0)_{+-a, c} = W (b_c +- 4 E_ac), W = 1/8, E_ac = V_a B_c - B_a V_c
+        const R lE = R(0.5) * ob * (mg[(4 + a) * 3 + c] - mg[(1 + a) * 3 + c]);
+        lV[a] += lE * B[c];
+        lB[c] += lE * V[a];
+        lB[a] -= lE * V[c];
+        lV[c] -= lE * B[a];
+      }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      lU[a] += lV[a];
+      lJ[a] = -k.alpha * lV[a];
+    }
+  }
+
+  // ---- current from the moments: J = N / D, N = r - kk r x B + kk^2 (r.B) B, D = 1 + kk^2 |B|^2,
+  //      r = -4 w_B J0, J0 = A(Lambda) - 2 U x B
+  if (MOMENT) {
+    const R kk = R(8) * k.alpha * k.omega_b;
+    const R kk2 = kk * kk;
+    const R D = R(1) + kk2 * (B[0] * B[0] + B[1] * B[1] + B[2] * B[2]);
+    const R j0[3] = {lam[1][2] - lam[2][1] - R(2) * (U[1] * B[2] - U[2] * B[1]),
+                     lam[2][0] - lam[0][2] - R(2) * (U[2] * B[0] - U[0] * B[2]),
+                     lam[0][1] - lam[1][0] - R(2) * (U[0] * B[1] - U[1] * B[0])};
+    const R r[3] = {R(-4) * k.omega_b * j0[0], R(-4) * k.omega_b * j0[1], R(-4) * k.omega_b * j0[2]};
+    const R lN[3] = {lJ[0] / D, lJ[1] / D, lJ[2] / D};
+    const R lD = -(lJ[0] * J[0] + lJ[1] * J[1] + lJ[2] * J[2]) / D;
+    const R BlN = B[0] * lN[0] + B[1] * lN[1] + B[2] * lN[2];
+    const R rB = r[0] * B[0] + r[1] * B[1] + r[2] * B[2];
+    // d/dr:  lN - kk (B x lN) + kk^2 (B.lN) B
+    const R Bxl[3] = {B[1] * lN[2] - B[2] * lN[1], B[2] * lN[0] - B[0] * lN[2], B[0] * lN[1] - B[1] * lN[0]};
+    R lr[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) lr[a] = lN[a] - kk * Bxl[a] + kk2 * BlN * B[a];
+    // d/dB: -kk (lN x r) + kk^2 ((B.lN) r + (r.B) lN) + 2 kk^2 lD B
+    const R lxr[3] = {lN[1] * r[2] - lN[2] * r[1], lN[2] * r[0] - lN[0] * r[2], lN[0] * r[1] - lN[1] * r[0]};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) lB[a] += -kk * lxr[a] + kk2 * (BlN * r[a] + rB * lN[a]) + R(2) * kk2 * lD * B[a];
+    const R lj0[3] = {R(-4) * k.omega_b * lr[0], R(-4) * k.omega_b * lr[1], R(-4) * k.omega_b * lr[2]};
+    // J0 = A - 2 U x B: d/dU = -2 (B x lj0), d/dB = -2 (lj0 x U)
+    const R Bxj[3] = {B[1] * lj0[2] - B[2] * lj0[1], B[2] * lj0[0] - B[0] * lj0[2], B[0] * lj0[1] - B[1] * lj0[0]};
+    const R jxU[3] = {lj0[1] * U[2] - lj0[2] * U[1], lj0[2] * U[0] - lj0[0] * U[2], lj0[0] * U[1] - lj0[1] * U[0]};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      lU[a] += R(-2) * Bxj[a];
+      lB[a] += R(-2) * jxU[a];
+    }
+    llam[1][2] += lj0[0]; llam[2][1] -= lj0[0];
+    llam[2][0] += lj0[1]; llam[0][2] -= lj0[1];
+    llam[0][1] += lj0[2]; llam[1][0] -= lj0[2];
+    lJ[0] = lJ[1] = lJ[2] = R(0);
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) lb[a] += lB[a];
+
+  // ---- fluid: f*_i = w_i (rho E_i - 1) + Maxwell_i(b) + sum_p Q_p H^p_i(U) + sum_a (F_a/2) H^a_i(U)
+  {
+    const R om1 = R(1) - k.omega;
+    const R kxx = m.sxx - rho * U[0] * U[0] + U[0] * F[0] + b[0] * (R(2) * b0[0] + b[0]);
+    const R kyy = m.syy - rho * U[1] * U[1] + U[1] * F[1] + b[1] * (R(2) * b0[1] + b[1]);
+    const R kzz = m.szz - rho * U[2] * U[2] + U[2] * F[2] + b[2] * (R(2) * b0[2] + b[2]);
+    const R tr = (kxx + kyy + kzz) * R(1.0 / 3.0);
+    const R qxx = om1 * (kxx - tr), qyy = om1 * (kyy - tr), qzz = om1 * (kzz - tr);
+    const R qxy = om1 * (m.sxy - rho * U[0] * U[1] + R(0.5) * (U[0] * F[1] + F[0] * U[1])
+                         + b0[0] * b[1] + b[0] * b0[1] + b[0] * b[1]);
+    const R qxz = om1 * (m.sxz - rho * U[0] * U[2] + R(0.5) * (U[0] * F[2] + F[0] * U[2])
+                         + b0[0] * b[2] + b[0] * b0[2] + b[0] * b[2]);
+    const R qyz = om1 * (m.syz - rho * U[1] * U[2] + R(0.5) * (U[1] * F[2] + F[1] * U[2])
+                         + b0[1] * b[2] + b[1] * b0[2] + b[1] * b[2]);
+    const R fhx = R(0.5) * F[0], fhy = R(0.5) * F[1], fhz = R(0.5) * F[2];
+    const Axis<R> ax(U[0]), ay(U[1]), az(U[2]);
+    const AxisD<R> dx(U[0]), dy(U[1]), dz(U[2]);
+    R lqxx = R(0), lqyy = R(0), lqzz = R(0), lqxy = R(0), lqxz = R(0), lqyz = R(0);
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+      const int x = cq(i, 0) + 1, y = cq(i, 1) + 1, z = cq(i, 2) + 1;
+      const R mu = mf[i];
+      const R w = R(wq(i));
+      const R ex = R(1) + ax.e[x], ey = R(1) + ay.e[y], ez = R(1) + az.e[z];
+      lrho += mu * w * ex * ey * ez;
+      const R wr = mu * w * rho;
+      lU[0] += wr * dx.de[x] * ey * ez;
+      lU[1] += wr * ex * dy.de[y] * ez;
+      lU[2] += wr * ex * ey * dz.de[z];
+      const R Bc = R(cq(i, 0)) * B[0] + R(cq(i, 1)) * B[1] + R(cq(i, 2)) * B[2];
+      const R wm45 = mu * w * R(4.5);
+      const R c2 = R(speed2q(i) - 1.0 / 3.0);
+      lb[0] += wm45 * (B[0] * c2 - R(2 * cq(i, 0)) * Bc);
+      lb[1] += wm45 * (B[1] * c2 - R(2 * cq(i, 1)) * Bc);
+      lb[2] += wm45 * (B[2] * c2 - R(2 * cq(i, 2)) * Bc);
+      const R h0x = ax.h0[x], h0y = ay.h0[y], h0z = az.h0[z];
+      const R h1x = ax.h1[x], h1y = ay.h1[y], h1z = az.h1[z];
+      const R h2x = ax.h2[x], h2y = ay.h2[y], h2z = az.h2[z];
+      const R d0x = dx.dh0[x], d0y = dy.dh0[y], d0z = dz.dh0[z];
+      const R d1x = dx.dh1[x], d1y = dy.dh1[y], d1z = dz.dh1[z];
+      lqxx += mu * h2x * h0y * h0z;
+      lqyy += mu * h0x * h2y * h0z;
+      lqzz += mu * h0x * h0y * h2z;
+      lqxy += mu * h1x * h1y * h0z;
+      lqxz += mu * h1x * h0y * h1z;
+      lqyz += mu * h0x * h1y * h1z;
+      lU[0] += mu * (qyy * d0x * h2y * h0z + qzz * d0x * h0y * h2z + qxy * d1x * h1y * h0z + qxz * d1x * h0y * h1z
+                     + qyz * d0x * h1y * h1z + fhx * d1x * h0y * h0z + fhy * d0x * h1y * h0z + fhz * d0x * h0y * h1z);
+      lU[1] += mu * (qxx * h2x * d0y * h0z + qzz * h0x * d0y * h2z + qxy * h1x * d1y * h0z + qxz * h1x * d0y * h1z
+                     + qyz * h0x * d1y * h1z + fhx * h1x * d0y * h0z + fhy * h0x * d1y * h0z + fhz * h0x * d0y * h1z);
+      lU[2] += mu * (qxx * h2x * h0y * d0z + qyy * h0x * h2y * d0z + qxy * h1x * h1y * d0z + qxz * h1x * h0y * d1z
+                     + qyz * h0x * h1y * d1z + fhx * h1x * h0y * d0z + fhy * h0x * h1y * d0z + fhz * h0x * h0y * d1z);
+    }
+    // Q = (1 - w) (K - tr K / 3 I): the deviatoric projection is self-adjoint
+    const R ltr = (lqxx + lqyy + lqzz) * R(1.0 / 3.0);
+    const R lk[3] = {om1 * (lqxx - ltr), om1 * (lqyy - ltr), om1 * (lqzz - ltr)};
+    const R lkxy = om1 * lqxy, lkxz = om1 * lqxz, lkyz = om1 * lqyz;
+    R ls2[6];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      ls2[a] = lk[a];
+      lrho -= lk[a] * U[a] * U[a];
+      lU[a] += lk[a] * (R(-2) * rho * U[a] + F[a]);
+      lb[a] += lk[a] * R(2) * B[a];
+    }
+    const int pa[3] = {0, 0, 1}, pb[3] = {1, 2, 2};
+    const R lko[3] = {lkxy, lkxz, lkyz};
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+      const int a = pa[p], c = pb[p];
+      ls2[3 + p] = lko[p];
+      lrho -= lko[p] * U[a] * U[c];
+      lU[a] += lko[p] * (-rho * U[c] + R(0.5) * F[c]);
+      lU[c] += lko[p] * (-rho * U[a] + R(0.5) * F[a]);
+      lb[a] += lko[p] * B[c];
+      lb[c] += lko[p] * B[a];
+    }
+    // U = (j + F/2) / rho
+    const R lj[3] = {lU[0] * inv_rho, lU[1] * inv_rho, lU[2] * inv_rho};
+    lrho -= (lU[0] * U[0] + lU[1] * U[1] + lU[2] * U[2]) * inv_rho;
+    // moments: d rho = sum f, j = sum f c, S2 = sum f c c
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+      const int cx = cq(i, 0), cy = cq(i, 1), cz = cq(i, 2);
+      lf[i] = lrho + R(cx) * lj[0] + R(cy) * lj[1] + R(cz) * lj[2] + R(cx * cx) * ls2[0] + R(cy * cy) * ls2[1]
+            + R(cz * cz) * ls2[2] + R(cx * cy) * ls2[3] + R(cx * cz) * ls2[4] + R(cy * cz) * ls2[5];
+    }
+  }
+  // ---- magnetic moments: b_c = sum_i g_ic (+ S/2), Lambda_ac = g_{+a,c} - g_{-a,c}
+#pragma unroll
+  for (int i = 0; i < 7; ++i)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) lg[i * 3 + c] += lb[c];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      lg[(4 + a) * 3 + c] += llam[a][c];
+      lg[(1 + a) * 3 + c] -= llam[a][c];
+    }
+}
+
 // Periodic neighbour of a node.
-__device__ __forceinline__ int wrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+FLAME_HD int wrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
 }  // namespace flame

@@ -1,0 +1,64 @@
+// Host build of the library's per-node arithmetic (test infrastructure): lets the CPU test
+// suite check the kernels' collision and its reverse pass against the oracle without a GPU.
+#include "../../paper_2212_11024_amd/csrc/flame_device.h"
+
+using namespace flame;
+
+namespace {
+PhysConst<double> consts(const double* p) {
+  PhysConst<double> k;
+  k.omega = p[0];
+  k.omega_b = p[1];
+  k.alpha = p[2];
+  k.b0[0] = p[3];
+  k.b0[1] = p[4];
+  k.b0[2] = p[5];
+  return k;
+}
+}  // namespace
+
+extern "C" {
+
+// One node's collision on deviations. params = {omega, omega_b, alpha, b0x, b0y, b0z}.
+// moment != 0: J from the moments (J_in ignored); else J = J_in. J_out receives the J used.
+void hc_collide(int moment, const double* f_in, const double* g_in, const double* Fin, const double* Sin,
+                const double* J_in, const double* params, double* f_out, double* g_out, double* J_out) {
+  const PhysConst<double> k = consts(params);
+  double f[kQ], g[kM], F[3], S[3];
+  for (int i = 0; i < kQ; ++i) f[i] = f_in[i];
+  for (int i = 0; i < kM; ++i) g[i] = g_in[i];
+  for (int c = 0; c < 3; ++c) { F[c] = Fin[c]; S[c] = Sin[c]; }
+  const FluidMoments<double> m = fluid_moments(f);
+  const double rho = 1.0 + m.drho;
+  const double U[3] = {(m.jx + 0.5 * F[0]) / rho, (m.jy + 0.5 * F[1]) / rho, (m.jz + 0.5 * F[2]) / rho};
+  double b[3], lam[3][3];
+  magnetic_moments(g, b, lam);
+  for (int c = 0; c < 3; ++c) b[c] += 0.5 * S[c];
+  const double B[3] = {k.b0[0] + b[0], k.b0[1] + b[1], k.b0[2] + b[2]};
+  double J[3];
+  if (moment) current_from_moments(lam, U, B, k.alpha, k.omega_b, J);
+  else for (int c = 0; c < 3; ++c) J[c] = J_in[c];
+  const double b0[3] = {k.b0[0], k.b0[1], k.b0[2]};
+  collide_fluid(f, m, rho, U, b, b0, F, k.omega);
+  collide_magnetic(g, U, B, b, J, S, k.alpha, k.omega_b);
+  for (int i = 0; i < kQ; ++i) f_out[i] = f[i];
+  for (int i = 0; i < kM; ++i) g_out[i] = g[i];
+  for (int c = 0; c < 3; ++c) J_out[c] = J[c];
+}
+
+void hc_collide_vjp(int moment, const double* f_in, const double* g_in, const double* Fin, const double* Sin,
+                    const double* J_in, const double* params, const double* mf_in, const double* mg_in,
+                    double* lf_out, double* lg_out, double* lJ_out) {
+  const PhysConst<double> k = consts(params);
+  double f[kQ], g[kM], F[3], S[3], J[3], mf[kQ], mg[kM], lf[kQ], lg[kM], lJ[3];
+  for (int i = 0; i < kQ; ++i) { f[i] = f_in[i]; mf[i] = mf_in[i]; }
+  for (int i = 0; i < kM; ++i) { g[i] = g_in[i]; mg[i] = mg_in[i]; }
+  for (int c = 0; c < 3; ++c) { F[c] = Fin[c]; S[c] = Sin[c]; J[c] = J_in[c]; }
+  if (moment) collide_vjp<double, true>(f, g, F, S, J, k, mf, mg, lf, lg, lJ);
+  else collide_vjp<double, false>(f, g, F, S, J, k, mf, mg, lf, lg, lJ);
+  for (int i = 0; i < kQ; ++i) lf_out[i] = lf[i];
+  for (int i = 0; i < kM; ++i) lg_out[i] = lg[i];
+  for (int c = 0; c < 3; ++c) lJ_out[c] = lJ[c];
+}
+
+}  // extern "C"

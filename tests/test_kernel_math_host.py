@@ -1,0 +1,122 @@
+"""The kernels' per-node arithmetic (compiled for the host from the same header the HIP
+kernels use) against the oracle: forward collision, and the hand-written reverse pass against
+torch autograd through the oracle's collision (the definition route, T-matrix)."""
+
+import ctypes
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import collision, current, equilibrium, scheme
+from oracle.lattice import C, WM, XI, omega_fluid, omega_magnetic
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+D = ctypes.POINTER(ctypes.c_double)
+
+
+@pytest.fixture(scope="module")
+def hc(tmp_path_factory):
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available")
+    out = str(tmp_path_factory.mktemp("hc") / "hc.so")
+    subprocess.run([hipcc, "-O2", "-std=c++17", "-fPIC", "-shared", "--offload-host-only", "-x", "hip",
+                    os.path.join(HERE, "hostcheck", "flame_hostcheck.hip"), "-o", out], check=True,
+                   stderr=subprocess.DEVNULL)
+    lib = ctypes.CDLL(out)
+    lib.hc_collide.argtypes = [ctypes.c_int] + [D] * 9
+    lib.hc_collide_vjp.argtypes = [ctypes.c_int] + [D] * 11
+    return lib
+
+
+def _p(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(D)
+
+
+def _case(rng, forced=True):
+    nu, eta, d_i = rng.uniform(0.005, 0.05), rng.uniform(0.005, 0.05), rng.uniform(0.0, 6.0)
+    b0 = rng.normal(0, 0.05, 3)
+    params = scheme.Params(1, 1, 1, nu, eta, d_i, tuple(b0))
+    rest = scheme.rest_state(params)
+    U = rng.normal(0, 0.04, 3)
+    B = b0 + rng.normal(0, 0.05, 3)
+    f = equilibrium.f_mhd_eq(torch.ones(1, dtype=torch.float64), torch.tensor(U).view(3, 1),
+                             torch.tensor(B).view(3, 1))[:, 0].numpy() + rng.normal(0, 2e-4, 27)
+    g = (WM.view(7, 1) * torch.tensor(B).view(1, 3)).numpy() + rng.normal(0, 3e-3, (7, 3))
+    F = rng.normal(0, 1e-4, 3) if forced else np.zeros(3)
+    S = rng.normal(0, 1e-4, 3) if forced else np.zeros(3)
+    J = rng.normal(0, 0.01, 3)
+    kp = np.array([omega_fluid(nu), omega_magnetic(eta), d_i, *b0])
+    return params, rest, f, g, F, S, J, kp
+
+
+def _oracle_node(f, g, F, S, params, J=None):
+    """Oracle collision of one node (full values) as a differentiable torch function."""
+    f2 = f.view(27, 1)
+    g2 = g.view(7, 3, 1)
+    rho = f2.sum(0)
+    mom = torch.einsum("in,ia->an", f2, C) + 0.5 * F.view(3, 1)
+    U = mom / rho
+    B = g2.sum(0) + 0.5 * S.view(3, 1)
+    lam = torch.einsum("ia,ibn->abn", XI, g2)
+    if J is None:
+        J = current.current_moment(lam, U, B, params.d_i, params.omega_b)
+    else:
+        J = J.view(3, 1)
+    fs = collision.collide_T(f2, rho, U, B, params.omega, F=F.view(3, 1))
+    gs = g2 - params.omega_b * (g2 - equilibrium.g_eq_hall(U, B, J, params.d_i))
+    gs = gs + (1.0 - 0.5 * params.omega_b) * WM.view(7, 1, 1) * S.view(1, 3, 1)
+    return fs.reshape(27), gs.reshape(21)
+
+
+@pytest.mark.parametrize("moment", [1, 0])
+def test_forward_collision_matches_oracle(hc, moment):
+    rng = np.random.default_rng(10 + moment)
+    for _ in range(20):
+        params, rest, f, g, F, S, J, kp = _case(rng)
+        fr, gr = rest.f[:, 0, 0, 0].numpy(), rest.g[:, :, 0, 0, 0].reshape(21).numpy()
+        df, pdf = _p(f - fr)
+        dg, pdg = _p(g.reshape(21) - gr)
+        fo, pfo = _p(np.zeros(27))
+        go, pgo = _p(np.zeros(21))
+        jo, pjo = _p(np.zeros(3))
+        hc.hc_collide(moment, pdf, pdg, _p(F)[1], _p(S)[1], _p(J)[1], _p(kp)[1], pfo, pgo, pjo)
+        t = lambda a: torch.tensor(a, dtype=torch.float64)  # noqa: E731
+        ofs, ogs = _oracle_node(t(f), t(g), t(F), t(S), params, None if moment else t(J))
+        assert np.abs(fo - (ofs.numpy() - fr)).max() < 1e-15
+        assert np.abs(go - (ogs.numpy() - gr)).max() < 1e-15
+
+
+@pytest.mark.parametrize("moment", [1, 0])
+def test_reverse_pass_matches_autograd(hc, moment):
+    rng = np.random.default_rng(20 + moment)
+    for _ in range(20):
+        params, rest, f, g, F, S, J, kp = _case(rng)
+        fr, gr = rest.f[:, 0, 0, 0].numpy(), rest.g[:, :, 0, 0, 0].reshape(21).numpy()
+        mf = rng.normal(0, 1, 27)
+        mg = rng.normal(0, 1, 21)
+        tf = torch.tensor(f, dtype=torch.float64, requires_grad=True)
+        tg = torch.tensor(g, dtype=torch.float64, requires_grad=True)
+        tJ = torch.tensor(J, dtype=torch.float64, requires_grad=True)
+        t = lambda a: torch.tensor(a, dtype=torch.float64)  # noqa: E731
+        ofs, ogs = _oracle_node(tf, tg, t(F), t(S), params, None if moment else tJ)
+        loss = (ofs * t(mf)).sum() + (ogs * t(mg)).sum()
+        inputs = (tf, tg) if moment else (tf, tg, tJ)
+        grads = torch.autograd.grad(loss, inputs)
+        lf, plf = _p(np.zeros(27))
+        lg, plg = _p(np.zeros(21))
+        lJ, plJ = _p(np.zeros(3))
+        hc.hc_collide_vjp(moment, _p(f - fr)[1], _p(g.reshape(21) - gr)[1], _p(F)[1], _p(S)[1], _p(J)[1],
+                          _p(kp)[1], _p(mf)[1], _p(mg)[1], plf, plg, plJ)
+        scale = float(max(grads[0].abs().max(), grads[1].abs().max()))
+        assert np.abs(lf - grads[0].numpy()).max() < 1e-12 * scale
+        assert np.abs(lg - grads[1].reshape(21).numpy()).max() < 1e-12 * scale
+        if moment:
+            assert np.abs(lJ).max() == 0.0
+        else:
+            assert np.abs(lJ - grads[2].numpy()).max() < 1e-12 * max(1.0, float(grads[2].abs().max()))
