@@ -158,6 +158,35 @@ flame_status flame_set_populations(flame_ctx* c, const double* src, int32_t devi
 flame_status flame_gather(flame_ctx* c, const int64_t* cells, int64_t n, double* out,
                           int32_t deviations);
 
+/* ---- Reverse mode (adjoint of the step; not part of the paper's method) ----------------------
+ * Arrays below are in the arithmetic type A (double for FLAME_F64, float otherwise), canonical
+ * order, node stride n = nx*ny*nz: "state" [48 + 3][n] = pre-collision deviations (27 fluid,
+ * 7 x 3 magnetic) followed by the J each node used; "lam" [48][n] = d loss / d(canonical
+ * deviations) at one time. All are device pointers, caller-owned, asynchronous. */
+
+/* One step, like flame_step(c, 1), that also writes the state it advanced from into state. */
+flame_status flame_step_save(flame_ctx* c, void* state);
+
+/* lam = (d step / d x)^T lam_next at the state saved by flame_step_save: the gather that
+ * transposes streaming, then the reverse pass of every node's collision (moments, J on the
+ * moment route, central-moment fluid and Hall magnetic collisions, forcing). On the stencil
+ * route lam_j ([3][n] scratch) receives d loss / dJ and its transpose-curl is added to the
+ * magnetic adjoints. lam must not alias lam_next. */
+flame_status flame_adjoint_step(flame_ctx* c, const void* state, const void* lam_next, void* lam,
+                                void* lam_j);
+
+/* lam = adjoint of the current state for a loss of its node fields: dl_du, dl_db (device
+ * double [3][n], nullable = zero) are d loss / du and d loss / dB with u, B as flame_moments
+ * returns them. */
+flame_status flame_adjoint_fields(flame_ctx* c, const double* dl_du, const double* dl_db, void* lam);
+
+/* Adjoint of the initial state of flame_init: from lam0 (d loss / d initial deviations) and the
+ * same u, b, grad_u, grad_b that flame_init received, write g_u, g_b (device double [3][n]) and,
+ * when non-NULL, g_grad_u, g_grad_b ([3][3][n]). */
+flame_status flame_adjoint_init(flame_ctx* c, const void* lam0, const double* u, const double* b,
+                                const double* grad_u, const double* grad_b, double* g_u, double* g_b,
+                                double* g_grad_u, double* g_grad_b);
+
 /* Number of steps taken since flame_init / flame_set_populations. */
 int64_t flame_step_count(const flame_ctx* c);
 

@@ -51,6 +51,10 @@ _SIGNATURES = {
     "flame_get_populations": (ctypes.c_int32, [_P, _P, ctypes.c_int32]),
     "flame_set_populations": (ctypes.c_int32, [_P, _P, ctypes.c_int32]),
     "flame_gather": (ctypes.c_int32, [_P, _P, ctypes.c_int64, _P, ctypes.c_int32]),
+    "flame_step_save": (ctypes.c_int32, [_P, _P]),
+    "flame_adjoint_step": (ctypes.c_int32, [_P, _P, _P, _P, _P]),
+    "flame_adjoint_fields": (ctypes.c_int32, [_P, _P, _P, _P]),
+    "flame_adjoint_init": (ctypes.c_int32, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "flame_step_count": (ctypes.c_int64, [_P]),
     "flame_cfl_number": (ctypes.c_double, [_P]),
     "flame_last_error": (ctypes.c_char_p, [_P]),
@@ -145,6 +149,23 @@ def flame_set_populations(ctx: int, src: int, deviations: int = 0) -> int:
 
 def flame_gather(ctx: int, cells: int, n: int, out: int, deviations: int = 0) -> int:
     return _check(load().flame_gather(ctx, cells, n, out, deviations), ctx)
+
+
+def flame_step_save(ctx: int, state: int) -> int:
+    return _check(load().flame_step_save(ctx, state), ctx)
+
+
+def flame_adjoint_step(ctx: int, state: int, lam_next: int, lam: int, lam_j: int) -> int:
+    return _check(load().flame_adjoint_step(ctx, state, lam_next, lam, lam_j), ctx)
+
+
+def flame_adjoint_fields(ctx: int, dl_du: int, dl_db: int, lam: int) -> int:
+    return _check(load().flame_adjoint_fields(ctx, dl_du, dl_db, lam), ctx)
+
+
+def flame_adjoint_init(ctx: int, lam0: int, u: int, b: int, grad_u: int, grad_b: int, g_u: int, g_b: int,
+                       g_grad_u: int, g_grad_b: int) -> int:
+    return _check(load().flame_adjoint_init(ctx, lam0, u, b, grad_u, grad_b, g_u, g_b, g_grad_u, g_grad_b), ctx)
 
 
 def flame_step_count(ctx: int) -> int:

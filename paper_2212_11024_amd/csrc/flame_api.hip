@@ -195,60 +195,22 @@ __global__ __launch_bounds__(256) void init_kernel(InitArgs<S> a) {
   if (a.gb)
     for (int p = 0; p < 3; ++p)
       for (int q = 0; q < 3; ++q) gb[p][q] = a.gb[(p * 3 + q) * n + cell];
-
-  // fluid: equilibrium at rho = 1, deviatoric first-order stress, and -F/2 first moment.
-  // These are the post-collision closed-form pieces with (1 - omega) P replaced by the
-  // initial non-equilibrium stress P0 and +F/2 by -F/2.
-  double P[3][3] = {};
-  if (a.noneq && a.gu) {
-    const double div = gu[0][0] + gu[1][1] + gu[2][2];
-    const double s = -(1.0 / 3.0) / a.omega;
-    for (int p = 0; p < 3; ++p)
-      for (int q = 0; q < 3; ++q)
-        P[p][q] = s * (gu[p][q] + gu[q][p] - (p == q ? 2.0 / 3.0 * div : 0.0));
-  }
-  const Axis<double> ax(U[0]), ay(U[1]), az(U[2]);
-  const double s = a.b0[0] * b[0] + a.b0[1] * b[1] + a.b0[2] * b[2]
-                 + 0.5 * (b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
-  for (int i = 0; i < kQ; ++i) {
-    const int x = cq(i, 0) + 1, y = cq(i, 1) + 1, z = cq(i, 2) + 1;
-    const double ex = ax.e[x], ey = ay.e[y], ez = az.e[z];
-    const double em1 = ex + (1.0 + ex) * (ey + (1.0 + ey) * ez);
-    const double w = wq(i);
-    double v = w * em1;
-    const double bc = cq(i, 0) * b[0] + cq(i, 1) * b[1] + cq(i, 2) * b[2];
-    const double b0c = cq(i, 0) * a.b0[0] + cq(i, 1) * a.b0[1] + cq(i, 2) * a.b0[2];
-    v += w * 4.5 * (s * (speed2q(i) - 1.0 / 3.0) - bc * (2.0 * b0c + bc));
-    const double h0x = ax.h0[x], h0y = ay.h0[y], h0z = az.h0[z];
-    const double h1x = ax.h1[x], h1y = ay.h1[y], h1z = az.h1[z];
-    const double h2x = ax.h2[x], h2y = ay.h2[y], h2z = az.h2[z];
-    v += P[0][0] * h2x * h0y * h0z + P[1][1] * h0x * h2y * h0z + P[2][2] * h0x * h0y * h2z
-       + P[0][1] * h1x * h1y * h0z + P[0][2] * h1x * h0y * h1z + P[1][2] * h0x * h1y * h1z;
-    v -= 0.5 * (F[0] * h1x * h0y * h0z + F[1] * h0x * h1y * h0z + F[2] * h0x * h0y * h1z);
-    a.F[static_cast<size_t>(i) * a.stride + a.at.f(i, px, py, pz)] = E::enc(v, E::fscale(i));
-  }
-  // magnetic: Hall equilibrium with J = curl b, first-order non-equilibrium, -S/2
-  double J[3] = {0, 0, 0};
-  if (a.gb) {
-    J[0] = gb[1][2] - gb[2][1];
-    J[1] = gb[2][0] - gb[0][2];
-    J[2] = gb[0][1] - gb[1][0];
-  }
-  const double V[3] = {U[0] - a.alpha * J[0], U[1] - a.alpha * J[1], U[2] - a.alpha * J[2]};
-  for (int i = 0; i < 7; ++i) {
-    for (int c = 0; c < 3; ++c) {
-      double xv = 0, xb = 0, xg = 0;
-      for (int p = 0; p < 3; ++p) {
-        xv += xim(i, p) * V[p];
-        xb += xim(i, p) * B[p];
-        xg += xim(i, p) * gb[p][c];
-      }
-      double v = wm(i) * (b[c] + 4.0 * (xv * B[c] - xb * V[c]));
-      if (a.noneq && a.gb) v -= wm(i) * xg / a.omega_b;
-      v -= 0.5 * wm(i) * Sb[c];
-      a.G[static_cast<size_t>(i * 3 + c) * a.stride + a.at.g(i, px, py, pz)] = E::enc(v, E::mscale(i));
-    }
-  }
+  PhysConst<double> k;
+  k.omega = a.omega;
+  k.omega_b = a.omega_b;
+  k.alpha = a.alpha;
+  for (int c = 0; c < 3; ++c) k.b0[c] = a.b0[c];
+  InitFlags fl;
+  fl.fluid_noneq = a.noneq && a.gu;
+  fl.mag_noneq = a.noneq && a.gb;
+  fl.has_H = a.gb != nullptr;
+  double f[kQ], g[kM];
+  init_node(U, b, gu, gb, F, Sb, k, fl, f, g);
+  for (int i = 0; i < kQ; ++i)
+    a.F[static_cast<size_t>(i) * a.stride + a.at.f(i, px, py, pz)] = E::enc(f[i], E::fscale(i));
+  for (int i = 0; i < 7; ++i)
+    for (int c = 0; c < 3; ++c)
+      a.G[static_cast<size_t>(i * 3 + c) * a.stride + a.at.g(i, px, py, pz)] = E::enc(g[i * 3 + c], E::mscale(i));
 }
 
 // ------------------------------------------------------------------ canonical copies
@@ -316,6 +278,43 @@ __global__ __launch_bounds__(256) void moments_kernel(AuxArgs<S> a, double* rho,
     if (B) B[c * n + cell] = q.B[c];
     if (J) J[c * n + cell] = q.J[c];
   }
+}
+
+// ------------------------------------------------------------------ adjoint of the node fields
+// lam = d loss / d(canonical deviations) for a loss of the node fields u = (j + F/2) / rho and
+// B = b0 + sum g + S/2: du_a / df_i = (c_ia - u_a) / rho, dB_c / dg_{i,c} = 1.
+template <typename S>
+__global__ __launch_bounds__(256) void adjoint_fields_kernel(View<S> v, const typename Enc<S>::R* force_u,
+                                                             const double* dl_du, const double* dl_db,
+                                                             typename Enc<S>::R* lam) {
+  using R = typename Enc<S>::R;
+  const size_t cell = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (cell >= v.n) return;
+  const size_t n = v.n;
+  int x, y, z;
+  node_xyz(cell, v.nx, v.ny, x, y, z);
+  double lu[3] = {0, 0, 0}, U[3] = {0, 0, 0}, rho = 1.0;
+  if (dl_du) {
+    double j[3] = {0, 0, 0};
+    for (int i = 0; i < kQ; ++i) {
+      const double fi = v.f(i, x, y, z);
+      rho += fi;
+      for (int c = 0; c < 3; ++c) j[c] += cq(i, c) * fi;
+    }
+    for (int c = 0; c < 3; ++c) {
+      const double F = force_u ? static_cast<double>(force_u[c * n + cell]) : 0.0;
+      U[c] = (j[c] + 0.5 * F) / rho;
+      lu[c] = dl_du[c * n + cell];
+    }
+  }
+  for (int i = 0; i < kQ; ++i) {
+    double s = 0.0;
+    for (int c = 0; c < 3; ++c) s += lu[c] * (cq(i, c) - U[c]);
+    lam[static_cast<size_t>(i) * n + cell] = static_cast<R>(s / rho);
+  }
+  for (int i = 0; i < 7; ++i)
+    for (int c = 0; c < 3; ++c)
+      lam[static_cast<size_t>(kQ + i * 3 + c) * n + cell] = static_cast<R>(dl_db ? dl_db[c * n + cell] : 0.0);
 }
 
 // ------------------------------------------------------------------ reductions
@@ -705,7 +704,7 @@ flame_status flame_step(flame_ctx* c, int64_t nsteps) {
   const bool two_g = mag_two_lattice(c->p);
   for (int64_t s = 0; s < nsteps; ++s) {
     const SetPtrs ptr = set_ptrs(c);
-    hipError_t e = launch_step(c, ptr);
+    hipError_t e = launch_step(c, ptr, nullptr);
     if (e != hipSuccess) return fail(c, FLAME_E_HIP, std::string("step kernel: ") + hipGetErrorString(e));
     if (two_f || two_g) c->cur ^= 1;
     if (!two_f || !two_g) c->parity ^= 1;
@@ -851,6 +850,20 @@ flame_status flame_gather(flame_ctx* c, const int64_t* cells, int64_t n, double*
     return hipGetLastError();
   });
   if (e != hipSuccess) return fail(c, FLAME_E_HIP, std::string("gather kernel: ") + hipGetErrorString(e));
+  return FLAME_OK;
+}
+
+flame_status flame_adjoint_fields(flame_ctx* c, const double* dl_du, const double* dl_db, void* lam) {
+  if (!c) return FLAME_E_INVAL;
+  if (!lam) return fail(c, FLAME_E_INVAL, "lam is NULL");
+  hipError_t e = by_storage(c, [&](auto tag) {
+    using S = decltype(tag);
+    using R = typename Enc<S>::R;
+    hipLaunchKernelGGL(adjoint_fields_kernel<S>, dim3(blocks_for(c->n, 256)), dim3(256), 0, c->stream,
+                       make_view<S>(c), static_cast<const R*>(c->p.force_u), dl_du, dl_db, static_cast<R*>(lam));
+    return hipGetLastError();
+  });
+  if (e != hipSuccess) return fail(c, FLAME_E_HIP, std::string("field adjoint kernel: ") + hipGetErrorString(e));
   return FLAME_OK;
 }
 

@@ -471,6 +471,162 @@ FLAME_HD void collide_vjp(const R (&f)[kQ], const R (&g)[kM], const R (&F)[3], c
     }
 }
 
+// ------------------------------------------------------------------ initial state of a node
+// Deviations of the initial populations at a node (rho = 1): fluid f^mhd(0)(1, u, B) plus the
+// first-order non-equilibrium stress P0 = -(c_s^2 / w)(G + G^T - 2/3 tr G I), G = grad u, and
+// -F/2 first central moment; magnetic g^Hall(0)(u, B, curl b) - (1/w_B) W_i xi_ia d_a b_c - S/2 W_i.
+// G[a][c] = d u_c / d x_a, H[a][c] = d b_c / d x_a (ignored unless the flags say present).
+struct InitFlags {
+  bool fluid_noneq;   // add the fluid non-equilibrium stress (needs G)
+  bool mag_noneq;     // add the magnetic non-equilibrium part (needs H)
+  bool has_H;         // J = curl b from H (else J = 0)
+};
+
+FLAME_HD void init_node(const double (&u)[3], const double (&b)[3], const double (&G)[3][3],
+                        const double (&H)[3][3], const double (&F)[3], const double (&S)[3],
+                        const PhysConst<double>& k, InitFlags fl, double (&f)[kQ], double (&g)[kM]) {
+  const double B[3] = {k.b0[0] + b[0], k.b0[1] + b[1], k.b0[2] + b[2]};
+  double P[3][3] = {};
+  if (fl.fluid_noneq) {
+    const double div = G[0][0] + G[1][1] + G[2][2];
+    const double s = -(1.0 / 3.0) / k.omega;
+    for (int p = 0; p < 3; ++p)
+      for (int q = 0; q < 3; ++q) P[p][q] = s * (G[p][q] + G[q][p] - (p == q ? 2.0 / 3.0 * div : 0.0));
+  }
+  const Axis<double> ax(u[0]), ay(u[1]), az(u[2]);
+  const double sb = k.b0[0] * b[0] + k.b0[1] * b[1] + k.b0[2] * b[2] + 0.5 * (b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+  for (int i = 0; i < kQ; ++i) {
+    const int x = cq(i, 0) + 1, y = cq(i, 1) + 1, z = cq(i, 2) + 1;
+    const double ex = ax.e[x], ey = ay.e[y], ez = az.e[z];
+    const double em1 = ex + (1.0 + ex) * (ey + (1.0 + ey) * ez);
+    const double w = wq(i);
+    double v = w * em1;
+    const double bc = cq(i, 0) * b[0] + cq(i, 1) * b[1] + cq(i, 2) * b[2];
+    const double b0c = cq(i, 0) * k.b0[0] + cq(i, 1) * k.b0[1] + cq(i, 2) * k.b0[2];
+    v += w * 4.5 * (sb * (speed2q(i) - 1.0 / 3.0) - bc * (2.0 * b0c + bc));
+    const double h0x = ax.h0[x], h0y = ay.h0[y], h0z = az.h0[z];
+    const double h1x = ax.h1[x], h1y = ay.h1[y], h1z = az.h1[z];
+    const double h2x = ax.h2[x], h2y = ay.h2[y], h2z = az.h2[z];
+    v += P[0][0] * h2x * h0y * h0z + P[1][1] * h0x * h2y * h0z + P[2][2] * h0x * h0y * h2z
+       + P[0][1] * h1x * h1y * h0z + P[0][2] * h1x * h0y * h1z + P[1][2] * h0x * h1y * h1z;
+    v -= 0.5 * (F[0] * h1x * h0y * h0z + F[1] * h0x * h1y * h0z + F[2] * h0x * h0y * h1z);
+    f[i] = v;
+  }
+  double J[3] = {0, 0, 0};
+  if (fl.has_H) {
+    J[0] = H[1][2] - H[2][1];
+    J[1] = H[2][0] - H[0][2];
+    J[2] = H[0][1] - H[1][0];
+  }
+  const double V[3] = {u[0] - k.alpha * J[0], u[1] - k.alpha * J[1], u[2] - k.alpha * J[2]};
+  for (int i = 0; i < 7; ++i)
+    for (int c = 0; c < 3; ++c) {
+      double xv = 0, xb = 0, xg = 0;
+      for (int p = 0; p < 3; ++p) {
+        xv += xim(i, p) * V[p];
+        xb += xim(i, p) * B[p];
+        xg += xim(i, p) * H[p][c];
+      }
+      double v = wm(i) * (b[c] + 4.0 * (xv * B[c] - xb * V[c]));
+      if (fl.mag_noneq) v -= wm(i) * xg / k.omega_b;
+      v -= 0.5 * wm(i) * S[c];
+      g[i * 3 + c] = v;
+    }
+}
+
+// Vector-Jacobian product of init_node: lf, lg = d loss / d(initial deviations) ->
+// gu, gb, gG, gH = d loss / d(u, b, G, H) at the node.
+FLAME_HD void init_node_vjp(const double (&u)[3], const double (&b)[3], const double (&G)[3][3],
+                            const double (&H)[3][3], const double (&F)[3], const PhysConst<double>& k,
+                            InitFlags fl, const double (&lf)[kQ], const double (&lg)[kM], double (&gu)[3],
+                            double (&gb)[3], double (&gG)[3][3], double (&gH)[3][3]) {
+  const double B[3] = {k.b0[0] + b[0], k.b0[1] + b[1], k.b0[2] + b[2]};
+  for (int a = 0; a < 3; ++a) {
+    gu[a] = gb[a] = 0.0;
+    for (int c = 0; c < 3; ++c) gG[a][c] = gH[a][c] = 0.0;
+  }
+  double P[3][3] = {};
+  const double s = -(1.0 / 3.0) / k.omega;
+  if (fl.fluid_noneq) {
+    const double div = G[0][0] + G[1][1] + G[2][2];
+    for (int p = 0; p < 3; ++p)
+      for (int q = 0; q < 3; ++q) P[p][q] = s * (G[p][q] + G[q][p] - (p == q ? 2.0 / 3.0 * div : 0.0));
+  }
+  const Axis<double> ax(u[0]), ay(u[1]), az(u[2]);
+  const AxisD<double> dx(u[0]), dy(u[1]), dz(u[2]);
+  double lP[6] = {0, 0, 0, 0, 0, 0};   // xx, yy, zz, xy, xz, yz
+  const double fhx = -0.5 * F[0], fhy = -0.5 * F[1], fhz = -0.5 * F[2];
+  for (int i = 0; i < kQ; ++i) {
+    const int x = cq(i, 0) + 1, y = cq(i, 1) + 1, z = cq(i, 2) + 1;
+    const double mu = lf[i];
+    const double w = wq(i);
+    const double ex = 1.0 + ax.e[x], ey = 1.0 + ay.e[y], ez = 1.0 + az.e[z];
+    gu[0] += mu * w * dx.de[x] * ey * ez;
+    gu[1] += mu * w * ex * dy.de[y] * ez;
+    gu[2] += mu * w * ex * ey * dz.de[z];
+    const double Bc = cq(i, 0) * B[0] + cq(i, 1) * B[1] + cq(i, 2) * B[2];
+    const double c2 = speed2q(i) - 1.0 / 3.0;
+    for (int d = 0; d < 3; ++d) gb[d] += mu * w * 4.5 * (B[d] * c2 - 2.0 * cq(i, d) * Bc);
+    const double h0x = ax.h0[x], h0y = ay.h0[y], h0z = az.h0[z];
+    const double h1x = ax.h1[x], h1y = ay.h1[y], h1z = az.h1[z];
+    const double h2x = ax.h2[x], h2y = ay.h2[y], h2z = az.h2[z];
+    const double d0x = dx.dh0[x], d0y = dy.dh0[y], d0z = dz.dh0[z];
+    const double d1x = dx.dh1[x], d1y = dy.dh1[y], d1z = dz.dh1[z];
+    lP[0] += mu * h2x * h0y * h0z;
+    lP[1] += mu * h0x * h2y * h0z;
+    lP[2] += mu * h0x * h0y * h2z;
+    lP[3] += mu * h1x * h1y * h0z;
+    lP[4] += mu * h1x * h0y * h1z;
+    lP[5] += mu * h0x * h1y * h1z;
+    const double qxx = P[0][0], qyy = P[1][1], qzz = P[2][2], qxy = P[0][1], qxz = P[0][2], qyz = P[1][2];
+    gu[0] += mu * (qyy * d0x * h2y * h0z + qzz * d0x * h0y * h2z + qxy * d1x * h1y * h0z + qxz * d1x * h0y * h1z
+                   + qyz * d0x * h1y * h1z + fhx * d1x * h0y * h0z + fhy * d0x * h1y * h0z + fhz * d0x * h0y * h1z);
+    gu[1] += mu * (qxx * h2x * d0y * h0z + qzz * h0x * d0y * h2z + qxy * h1x * d1y * h0z + qxz * h1x * d0y * h1z
+                   + qyz * h0x * d1y * h1z + fhx * h1x * d0y * h0z + fhy * h0x * d1y * h0z + fhz * h0x * d0y * h1z);
+    gu[2] += mu * (qxx * h2x * h0y * d0z + qyy * h0x * h2y * d0z + qxy * h1x * h1y * d0z + qxz * h1x * h0y * d1z
+                   + qyz * h0x * h1y * d1z + fhx * h1x * h0y * d0z + fhy * h0x * h1y * d0z + fhz * h0x * h0y * d1z);
+  }
+  if (fl.fluid_noneq) {
+    const double ltr = lP[0] + lP[1] + lP[2];
+    for (int a = 0; a < 3; ++a) gG[a][a] += s * (2.0 * lP[a] - 2.0 / 3.0 * ltr);
+    gG[0][1] += s * lP[3]; gG[1][0] += s * lP[3];
+    gG[0][2] += s * lP[4]; gG[2][0] += s * lP[4];
+    gG[1][2] += s * lP[5]; gG[2][1] += s * lP[5];
+  }
+  double J[3] = {0, 0, 0};
+  if (fl.has_H) {
+    J[0] = H[1][2] - H[2][1];
+    J[1] = H[2][0] - H[0][2];
+    J[2] = H[0][1] - H[1][0];
+  }
+  const double V[3] = {u[0] - k.alpha * J[0], u[1] - k.alpha * J[1], u[2] - k.alpha * J[2]};
+  double lV[3] = {0, 0, 0};
+  for (int i = 0; i < 7; ++i)
+    for (int c = 0; c < 3; ++c) {
+      const double mu = lg[i * 3 + c];
+      const double W = wm(i);
+      double xv = 0, xb = 0;
+      for (int p = 0; p < 3; ++p) {
+        xv += xim(i, p) * V[p];
+        xb += xim(i, p) * B[p];
+      }
+      gb[c] += mu * W * (1.0 + 4.0 * xv);
+      lV[c] -= mu * 4.0 * W * xb;
+      for (int d = 0; d < 3; ++d) {
+        gb[d] -= mu * 4.0 * W * xim(i, d) * V[c];
+        lV[d] += mu * 4.0 * W * xim(i, d) * B[c];
+        if (fl.mag_noneq) gH[d][c] -= mu * W * xim(i, d) / k.omega_b;
+      }
+    }
+  for (int a = 0; a < 3; ++a) gu[a] += lV[a];
+  if (fl.has_H) {
+    const double lJ[3] = {-k.alpha * lV[0], -k.alpha * lV[1], -k.alpha * lV[2]};
+    gH[1][2] += lJ[0]; gH[2][1] -= lJ[0];
+    gH[2][0] += lJ[1]; gH[0][2] -= lJ[1];
+    gH[0][1] += lJ[2]; gH[1][0] -= lJ[2];
+  }
+}
+
 // Periodic neighbour of a node.
 FLAME_HD int wrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 

@@ -65,6 +65,32 @@ inline bool mag_two_lattice(const flame_params& p) {
 }
 SetPtrs set_ptrs(const flame_ctx* c);
 
-hipError_t launch_step(const flame_ctx* c, const SetPtrs& s);
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2): hardware
+// workgroup h runs on XCD h % 8. Remap so that XCD j processes one contiguous range of logical
+// tiles (x fastest, then y, then z): neighbouring tiles, which share halo rows and the cache
+// lines that shifted stores straddle, then sit behind the same L2.
+#ifndef FLAME_XCD_REMAP
+#define FLAME_XCD_REMAP 1
+#endif
+constexpr unsigned kXCDs = 8;
+
+__device__ __forceinline__ void logical_block(unsigned gx, unsigned gy, unsigned gz, unsigned& bx, unsigned& by,
+                                              unsigned& bz) {
+  const unsigned total = gx * gy * gz;
+  const unsigned h = blockIdx.x;
+  unsigned l = h;
+  if (FLAME_XCD_REMAP) {
+    const unsigned q = total / kXCDs, r = total % kXCDs;
+    const unsigned j = h % kXCDs, k = h / kXCDs;
+    l = j * q + min(j, r) + k;
+  }
+  bx = l % gx;
+  by = (l / gx) % gy;
+  bz = l / (gx * gy);
+}
+
+// One fused step; with save != null also writes the pre-collision state of every node
+// (arithmetic type, [48 populations + 3 J][n]).
+hipError_t launch_step(const flame_ctx* c, const SetPtrs& s, void* save);
 
 }  // namespace flame

@@ -38,6 +38,7 @@ struct StepArgs {
   int zchunk;         // planes per workgroup (z-marching kernel)
   size_t n;           // nodes (stride of the caller's forcing arrays)
   size_t stride;      // elements between consecutive population arrays (n plus padding)
+  R* save;            // optional: pre-collision state [48 populations + 3 J][n] of this step
   PhysConst<R> k;
 };
 
@@ -87,30 +88,6 @@ struct Planes {
   }
   __device__ __forceinline__ uint32_t at(int dz) const { return p[dz + 1]; }
 };
-
-// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2): hardware
-// workgroup h runs on XCD h % 8. Remap so that XCD j processes one contiguous range of logical
-// tiles (x fastest, then y, then z): neighbouring tiles, which share halo rows and the cache
-// lines that shifted stores straddle, then sit behind the same L2.
-#ifndef FLAME_XCD_REMAP
-#define FLAME_XCD_REMAP 1
-#endif
-constexpr unsigned kXCDs = 8;
-
-__device__ __forceinline__ void logical_block(unsigned gx, unsigned gy, unsigned gz, unsigned& bx, unsigned& by,
-                                              unsigned& bz) {
-  const unsigned total = gx * gy * gz;
-  const unsigned h = blockIdx.x;
-  unsigned l = h;
-  if (FLAME_XCD_REMAP) {
-    const unsigned q = total / kXCDs, r = total % kXCDs;
-    const unsigned j = h % kXCDs, k = h / kXCDs;
-    l = j * q + min(j, r) + k;
-  }
-  bx = l % gx;
-  by = (l / gx) % gy;
-  bz = l / (gx * gy);
-}
 
 // Fluid populations of the node. FAA: in place (PAR selects the AA step); else pull.
 template <typename S, bool FAA, int PAR>
@@ -209,10 +186,24 @@ __device__ __forceinline__ void collide_node(R (&f)[kQ], R (&g)[kM], const Fluid
   collide_magnetic(g, U, B, b, J, Sb, k.alpha, k.omega_b);
 }
 
+// Record the node's pre-collision deviations (and the J it uses) for the adjoint.
+template <typename R>
+__device__ __forceinline__ void save_state(R* save, size_t n, uint32_t cell, const R (&f)[kQ], const R (&g)[kM]) {
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) save[static_cast<size_t>(q) * n + cell] = f[q];
+#pragma unroll
+  for (int q = 0; q < kM; ++q) save[static_cast<size_t>(kQ + q) * n + cell] = g[q];
+}
+template <typename R>
+__device__ __forceinline__ void save_current(R* save, size_t n, uint32_t cell, const R (&J)[3]) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) save[static_cast<size_t>(kQ + kM + c) * n + cell] = J[c];
+}
+
 // ------------------------------------------------------------------ moment-route kernel
 constexpr int kLocalThreads = 256;
 
-template <typename S, bool FAA, bool MAA, int PAR>
+template <typename S, bool FAA, bool MAA, int PAR, bool SAVE>
 __global__ __launch_bounds__(kLocalThreads) void step_local(StepArgs<S> a) {
   using R = typename Enc<S>::R;
   unsigned bx, by, bz;
@@ -229,6 +220,7 @@ __global__ __launch_bounds__(kLocalThreads) void step_local(StepArgs<S> a) {
   load_magnetic<S, MAA, PAR>(a, rw, pl, g);
   R F[3], Sb[3];
   forcing_at(a, cell, F, Sb);
+  if (SAVE) save_state(a.save, a.n, cell, f, g);
   const FluidMoments<R> m = fluid_moments(f);
   const R inv_rho = R(1) / (R(1) + m.drho);
   const R U[3] = {(m.jx + R(0.5) * F[0]) * inv_rho, (m.jy + R(0.5) * F[1]) * inv_rho,
@@ -240,6 +232,7 @@ __global__ __launch_bounds__(kLocalThreads) void step_local(StepArgs<S> a) {
   const R B[3] = {a.k.b0[0] + b[0], a.k.b0[1] + b[1], a.k.b0[2] + b[2]};
   R J[3];
   current_from_moments(lam, U, B, a.k.alpha, a.k.omega_b, J);
+  if (SAVE) save_current(a.save, a.n, cell, J);
   collide_node(f, g, m, U, b, J, F, Sb, a.k);
   store_fluid<S, FAA, PAR>(a, rw, pl, f);
   store_magnetic<S, MAA, PAR>(a, rw, pl, g);
@@ -266,7 +259,7 @@ struct Tile {
 };
 constexpr int kZChunk = FLAME_ZCHUNK;   // planes per workgroup
 
-template <typename S, bool FAA, int PAR>
+template <typename S, bool FAA, int PAR, bool SAVE>
 __global__ __launch_bounds__(kTX * Tile<typename Enc<S>::R>::ty, FLAME_ZMARCH_WAVES_PER_EU) void step_zmarch(
     StepArgs<S> a) {
   using E = Enc<S>;
@@ -357,6 +350,7 @@ __global__ __launch_bounds__(kTX * Tile<typename Enc<S>::R>::ty, FLAME_ZMARCH_WA
       R f[kQ];
       load_fluid<S, FAA, PAR>(a, rw, pl, f);
       forcing_at(a, cell, F, Sb);
+      if (SAVE) save_state(a.save, a.n, cell, f, g);
       const FluidMoments<R> m = fluid_moments(f);
       const R inv_rho = R(1) / (R(1) + m.drho);
       U[0] = (m.jx + R(0.5) * F[0]) * inv_rho;
@@ -379,6 +373,7 @@ __global__ __launch_bounds__(kTX * Tile<typename Enc<S>::R>::ty, FLAME_ZMARCH_WA
       J[1] = R(0.5) * (N[py][px][0] - P[py][px][0]) - R(0.5) * (C[py][px + 1][2] - C[py][px - 1][2]);
       J[2] = R(0.5) * (C[py][px + 1][1] - C[py][px - 1][1]) - R(0.5) * (C[py + 1][px][0] - C[py - 1][px][0]);
       const R B[3] = {a.k.b0[0] + b[0], a.k.b0[1] + b[1], a.k.b0[2] + b[2]};
+      if (SAVE) save_current(a.save, a.n, cell, J);
       collide_magnetic(g, U, B, b, J, Sb, a.k.alpha, a.k.omega_b);
       store_magnetic<S, false, 0>(a, rw, pl, g);
     }
@@ -390,8 +385,8 @@ __global__ __launch_bounds__(kTX * Tile<typename Enc<S>::R>::ty, FLAME_ZMARCH_WA
   }
 }
 
-template <typename S>
-static hipError_t launch_typed(const flame_ctx* c, const SetPtrs& s) {
+template <typename S, bool SAVE>
+static hipError_t launch_typed(const flame_ctx* c, const SetPtrs& s, void* save) {
   using R = typename Enc<S>::R;
   StepArgs<S> a;
   a.f_src = static_cast<const S*>(s.f_src);
@@ -405,6 +400,7 @@ static hipError_t launch_typed(const flame_ctx* c, const SetPtrs& s) {
   a.nz = c->p.nz;
   a.n = c->n;
   a.stride = c->stride;
+  a.save = static_cast<R*>(save);
   a.k.omega = R(c->omega);
   a.k.omega_b = R(c->omega_b);
   a.k.alpha = R(c->p.d_i);
@@ -416,30 +412,30 @@ static hipError_t launch_typed(const flame_ctx* c, const SetPtrs& s) {
     const dim3 block(kTX, kTY, 1);
     const dim3 grid(((c->p.nx + kTX - 1) / kTX) * ((c->p.ny + kTY - 1) / kTY) * ((c->p.nz + a.zchunk - 1) / a.zchunk));
     if (!s.fluid_aa)
-      hipLaunchKernelGGL((step_zmarch<S, false, 0>), grid, block, 0, c->stream, a);
+      hipLaunchKernelGGL((step_zmarch<S, false, 0, SAVE>), grid, block, 0, c->stream, a);
     else if (par == 0)
-      hipLaunchKernelGGL((step_zmarch<S, true, 0>), grid, block, 0, c->stream, a);
+      hipLaunchKernelGGL((step_zmarch<S, true, 0, SAVE>), grid, block, 0, c->stream, a);
     else
-      hipLaunchKernelGGL((step_zmarch<S, true, 1>), grid, block, 0, c->stream, a);
+      hipLaunchKernelGGL((step_zmarch<S, true, 1, SAVE>), grid, block, 0, c->stream, a);
   } else {
     a.zchunk = 1;
     const dim3 block(kLocalThreads, 1, 1);
     const dim3 grid(((c->p.nx + kLocalThreads - 1) / kLocalThreads) * c->p.ny * c->p.nz);
     if (!s.fluid_aa)
-      hipLaunchKernelGGL((step_local<S, false, false, 0>), grid, block, 0, c->stream, a);
+      hipLaunchKernelGGL((step_local<S, false, false, 0, SAVE>), grid, block, 0, c->stream, a);
     else if (par == 0)
-      hipLaunchKernelGGL((step_local<S, true, true, 0>), grid, block, 0, c->stream, a);
+      hipLaunchKernelGGL((step_local<S, true, true, 0, SAVE>), grid, block, 0, c->stream, a);
     else
-      hipLaunchKernelGGL((step_local<S, true, true, 1>), grid, block, 0, c->stream, a);
+      hipLaunchKernelGGL((step_local<S, true, true, 1, SAVE>), grid, block, 0, c->stream, a);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_step(const flame_ctx* c, const SetPtrs& s) {
+hipError_t launch_step(const flame_ctx* c, const SetPtrs& s, void* save) {
   switch (c->p.storage) {
-    case FLAME_F64: return launch_typed<double>(c, s);
-    case FLAME_F32: return launch_typed<float>(c, s);
-    default: return launch_typed<_Float16>(c, s);
+    case FLAME_F64: return save ? launch_typed<double, true>(c, s, save) : launch_typed<double, false>(c, s, save);
+    case FLAME_F32: return save ? launch_typed<float, true>(c, s, save) : launch_typed<float, false>(c, s, save);
+    default: return save ? launch_typed<_Float16, true>(c, s, save) : launch_typed<_Float16, false>(c, s, save);
   }
 }
 

@@ -62,3 +62,41 @@ void hc_collide_vjp(int moment, const double* f_in, const double* g_in, const do
 }
 
 }  // extern "C"
+
+extern "C" {
+
+// Initial deviations of one node. flags = {fluid_noneq, mag_noneq, has_H}.
+void hc_init(const double* u_in, const double* b_in, const double* G_in, const double* H_in, const double* Fin,
+             const double* Sin, const double* params, const int* flags, double* f_out, double* g_out) {
+  const PhysConst<double> k = consts(params);
+  double u[3], b[3], G[3][3], H[3][3], F[3], S[3], f[kQ], g[kM];
+  for (int a = 0; a < 3; ++a) {
+    u[a] = u_in[a]; b[a] = b_in[a]; F[a] = Fin[a]; S[a] = Sin[a];
+    for (int c = 0; c < 3; ++c) { G[a][c] = G_in[a * 3 + c]; H[a][c] = H_in[a * 3 + c]; }
+  }
+  InitFlags fl{flags[0] != 0, flags[1] != 0, flags[2] != 0};
+  init_node(u, b, G, H, F, S, k, fl, f, g);
+  for (int i = 0; i < kQ; ++i) f_out[i] = f[i];
+  for (int i = 0; i < kM; ++i) g_out[i] = g[i];
+}
+
+void hc_init_vjp(const double* u_in, const double* b_in, const double* G_in, const double* H_in, const double* Fin,
+                 const double* params, const int* flags, const double* lf_in, const double* lg_in, double* gu_out,
+                 double* gb_out, double* gG_out, double* gH_out) {
+  const PhysConst<double> k = consts(params);
+  double u[3], b[3], G[3][3], H[3][3], F[3], lf[kQ], lg[kM], gu[3], gb[3], gG[3][3], gH[3][3];
+  for (int a = 0; a < 3; ++a) {
+    u[a] = u_in[a]; b[a] = b_in[a]; F[a] = Fin[a];
+    for (int c = 0; c < 3; ++c) { G[a][c] = G_in[a * 3 + c]; H[a][c] = H_in[a * 3 + c]; }
+  }
+  for (int i = 0; i < kQ; ++i) lf[i] = lf_in[i];
+  for (int i = 0; i < kM; ++i) lg[i] = lg_in[i];
+  InitFlags fl{flags[0] != 0, flags[1] != 0, flags[2] != 0};
+  init_node_vjp(u, b, G, H, F, k, fl, lf, lg, gu, gb, gG, gH);
+  for (int a = 0; a < 3; ++a) {
+    gu_out[a] = gu[a]; gb_out[a] = gb[a];
+    for (int c = 0; c < 3; ++c) { gG_out[a * 3 + c] = gG[a][c]; gH_out[a * 3 + c] = gH[a][c]; }
+  }
+}
+
+}  // extern "C"

@@ -30,6 +30,9 @@ def hc(tmp_path_factory):
     lib = ctypes.CDLL(out)
     lib.hc_collide.argtypes = [ctypes.c_int] + [D] * 9
     lib.hc_collide_vjp.argtypes = [ctypes.c_int] + [D] * 11
+    I = ctypes.POINTER(ctypes.c_int)
+    lib.hc_init.argtypes = [D] * 7 + [I, D, D]
+    lib.hc_init_vjp.argtypes = [D] * 6 + [I] + [D] * 6
     return lib
 
 
@@ -120,3 +123,44 @@ def test_reverse_pass_matches_autograd(hc, moment):
             assert np.abs(lJ).max() == 0.0
         else:
             assert np.abs(lJ - grads[2].numpy()).max() < 1e-12 * max(1.0, float(grads[2].abs().max()))
+
+
+def _oracle_init(u, b, G, H, F, S, params, flags):
+    """Oracle initial state of one node (full values) as a differentiable torch function."""
+    p = scheme.Params(1, 1, 1, params.nu, params.eta, params.d_i, params.b0, "moment", "T",
+                      F.view(3, 1, 1, 1), S.view(3, 1, 1, 1))
+    st = scheme.init_state(p, u.view(3, 1, 1, 1), b.view(3, 1, 1, 1),
+                           G.view(3, 3, 1, 1, 1) if flags[0] else None,
+                           H.view(3, 3, 1, 1, 1) if flags[2] else None, noneq=bool(flags[0] or flags[1]))
+    return st.f.reshape(27), st.g.reshape(21)
+
+
+@pytest.mark.parametrize("flags", [(1, 1, 1), (0, 0, 1), (0, 0, 0)])
+def test_initial_state_and_its_reverse_pass(hc, flags):
+    rng = np.random.default_rng(30 + sum(flags))
+    fl = (ctypes.c_int * 3)(*flags)
+    for _ in range(10):
+        params, rest, _, _, F, S, _, kp = _case(rng)
+        u = rng.normal(0, 0.03, 3)
+        b = rng.normal(0, 0.03, 3)
+        G = rng.normal(0, 0.01, (3, 3))
+        H = rng.normal(0, 0.01, (3, 3))
+        fr, gr = rest.f[:, 0, 0, 0].numpy(), rest.g[:, :, 0, 0, 0].reshape(21).numpy()
+        fo, pfo = _p(np.zeros(27))
+        go, pgo = _p(np.zeros(21))
+        hc.hc_init(_p(u)[1], _p(b)[1], _p(G)[1], _p(H)[1], _p(F)[1], _p(S)[1], _p(kp)[1], fl, pfo, pgo)
+        tu, tb, tG, tH = (torch.tensor(a, dtype=torch.float64, requires_grad=True) for a in (u, b, G, H))
+        t = lambda a: torch.tensor(a, dtype=torch.float64)  # noqa: E731
+        of, og = _oracle_init(tu, tb, tG, tH, t(F), t(S), params, flags)
+        assert np.abs(fo - (of.detach().numpy() - fr)).max() < 1e-15
+        assert np.abs(go - (og.detach().numpy() - gr)).max() < 1e-15
+        lf = rng.normal(0, 1, 27)
+        lg = rng.normal(0, 1, 21)
+        loss = (of * t(lf)).sum() + (og * t(lg)).sum()
+        grads = torch.autograd.grad(loss, (tu, tb, tG, tH), allow_unused=True)
+        outs = [_p(np.zeros(n)) for n in (3, 3, 9, 9)]
+        hc.hc_init_vjp(_p(u)[1], _p(b)[1], _p(G)[1], _p(H)[1], _p(F)[1], _p(kp)[1], fl, _p(lf)[1], _p(lg)[1],
+                       *[o[1] for o in outs])
+        for (arr, _), ref in zip(outs, grads):
+            ref = np.zeros(arr.size) if ref is None else ref.numpy().reshape(-1)
+            assert np.abs(arr - ref).max() < 1e-12 * max(1.0, np.abs(ref).max())
