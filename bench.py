@@ -107,6 +107,69 @@ def time_variant(n, storage, jmode, steps, warmup, fields):
     }
 
 
+ADJ_PHYS = dict(nu=0.002, eta=0.002, d_i=4.0, b0=(0.0, 0.0, 0.0))
+
+
+def adjoint_timing(n=128, storage="f32", jmode="moment", seg=50):
+    """Cost of reverse mode on the adjoint workload (n^3, decaying-turbulence fields, nu = eta =
+    0.002, d_i = 4): one checkpoint segment of the backward sweep (restore, seg state-saving
+    steps, seg adjoint steps) against seg forward steps. The segment is swept once untimed first,
+    so that every buffer has been touched before the timed sweep."""
+    import torch
+    import synthetic
+    from paper_2212_11024_amd import _lib as L
+    from paper_2212_11024_amd.solver import Solver
+    shape = (n, n, n)
+    u, gu = synthetic.evaluate(synthetic.shell_field(0, 1, 4, 0.02), shape, "cuda")
+    b, gb = synthetic.evaluate(synthetic.shell_field(1, 1, 4, 0.02), shape, "cuda")
+    s = Solver(n, n, n, ADJ_PHYS["nu"], ADJ_PHYS["eta"], ADJ_PHYS["d_i"], ADJ_PHYS["b0"], storage, jmode, "aa",
+               u, b, gu, gb)
+    del u, b, gu, gb
+    adt = torch.float64 if storage == "f64" else torch.float32
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+    s.step(5)
+    ckf, ckg = s.get_populations(deviations=True)
+    ckf, ckg = ckf.clone(), ckg.clone()
+    states = torch.empty((seg, 51 * s.n), dtype=adt, device="cuda")
+    lam = torch.zeros(48 * s.n, dtype=adt, device="cuda")
+    lam2 = torch.empty_like(lam)
+    lam_j = torch.empty(3 * s.n, dtype=adt, device="cuda")
+
+    def segment(lam, lam2):
+        s.set_populations(ckf, ckg, deviations=True)
+        for k in range(seg):
+            L.flame_step_save(s.ctx, states[k].data_ptr())
+        mid = ev()
+        mid.record()
+        for k in reversed(range(seg)):
+            L.flame_adjoint_step(s.ctx, states[k].data_ptr(), lam.data_ptr(), lam2.data_ptr(), lam_j.data_ptr())
+            lam, lam2 = lam2, lam
+        return mid
+
+    segment(lam, lam2)
+    lam.zero_()
+    s.set_populations(ckf, ckg, deviations=True)
+    torch.cuda.synchronize()
+    e0, e1 = ev(), ev()
+    e0.record()
+    s.step(seg)
+    e1.record()
+    torch.cuda.synchronize()
+    t_fwd = e0.elapsed_time(e1)
+    e0, e2 = ev(), ev()
+    e0.record()
+    e1 = segment(lam, lam2)
+    e2.record()
+    torch.cuda.synchronize()
+    t_rec, t_adj = e0.elapsed_time(e1), e1.elapsed_time(e2)
+    s.close()
+    del states, lam, lam2, lam_j, s
+    torch.cuda.empty_cache()
+    return {"grid": [n, n, n], "storage": storage, "jmode": jmode, "segment_steps": seg,
+            "forward_ms_per_step": round(t_fwd / seg, 4), "recompute_ms_per_step": round(t_rec / seg, 4),
+            "adjoint_ms_per_step": round(t_adj / seg, 4), "ratio": round((t_rec + t_adj) / t_fwd, 3)}
+
+
 def copy_probe(gib=4, reps=5):
     """Plain device-to-device copy of a known size: achievable read+write bandwidth."""
     import torch
@@ -191,6 +254,12 @@ def main(argv=None):
         results.append(r)
     del fields
     torch.cuda.empty_cache()
+    adj = []
+    if args.variants == "all":
+        for jm in ("moment", "stencil"):
+            print(f"[bench] adjoint segment 128^3 f32 {jm}", file=sys.stderr, flush=True)
+            adj.append(adjoint_timing(128, "f32", jm))
+            print(f"[bench]   {adj[-1]}", file=sys.stderr, flush=True)
     head = results[0]
     traffic = None
     if n == 512 and kernel_fingerprint() == TRAFFIC_RECORD["fingerprint"]:
@@ -222,7 +291,8 @@ def main(argv=None):
                      "algorithmic_GB_per_launch": round(head["bytes_per_node"] * n ** 3 / 1e9, 3),
                      "bytes_per_node": head["bytes_per_node"]},
         "variants": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()} for r in results],
-        "adjoint_forward_ratio": None,
+        "adjoint_forward_ratio": (min(a["ratio"] for a in adj) if adj else None),
+        "adjoint": adj,
         "copy_probe": copy,
         "cpu_baseline": cpu,
     }

@@ -175,6 +175,18 @@ flame_status flame_step_save(flame_ctx* c, void* state);
 flame_status flame_adjoint_step(flame_ctx* c, const void* state, const void* lam_next, void* lam,
                                 void* lam_j);
 
+/* Trace lattices (moment route, AA layout): one time level laid out as a two-lattice pull
+ * source, 48 arrays [q][n] of the storage type (27 fluid, then 7 x 3 magnetic), node stride
+ * n = nx*ny*nz, with the stored encoding of the deviations; slot q at node y holds the
+ * post-collision population q of node y, so population q of node x at the next step is slot q
+ * at x - c_q. flame_trace_bytes(c) bytes each (0 if c is NULL). flame_trace_export writes the
+ * current state (exact: stored values are moved, not recoded); flame_trace_step advances a
+ * lattice src by one step into dst (dst must not alias src) without touching the context, and
+ * reproduces the context's own steps bitwise. Other routes and layouts get FLAME_E_INVAL. */
+size_t flame_trace_bytes(const flame_ctx* c);
+flame_status flame_trace_export(flame_ctx* c, void* lat);
+flame_status flame_trace_step(flame_ctx* c, const void* src, void* dst);
+
 /* lam = adjoint of the current state for a loss of its node fields: dl_du, dl_db (device
  * double [3][n], nullable = zero) are d loss / du and d loss / dB with u, B as flame_moments
  * returns them. */

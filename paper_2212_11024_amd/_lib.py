@@ -52,6 +52,9 @@ _SIGNATURES = {
     "flame_set_populations": (ctypes.c_int32, [_P, _P, ctypes.c_int32]),
     "flame_gather": (ctypes.c_int32, [_P, _P, ctypes.c_int64, _P, ctypes.c_int32]),
     "flame_step_save": (ctypes.c_int32, [_P, _P]),
+    "flame_trace_bytes": (ctypes.c_size_t, [_P]),
+    "flame_trace_export": (ctypes.c_int32, [_P, _P]),
+    "flame_trace_step": (ctypes.c_int32, [_P, _P, _P]),
     "flame_adjoint_step": (ctypes.c_int32, [_P, _P, _P, _P, _P]),
     "flame_adjoint_fields": (ctypes.c_int32, [_P, _P, _P, _P]),
     "flame_adjoint_init": (ctypes.c_int32, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
@@ -153,6 +156,18 @@ def flame_gather(ctx: int, cells: int, n: int, out: int, deviations: int = 0) ->
 
 def flame_step_save(ctx: int, state: int) -> int:
     return _check(load().flame_step_save(ctx, state), ctx)
+
+
+def flame_trace_bytes(ctx: int) -> int:
+    return int(load().flame_trace_bytes(ctx))
+
+
+def flame_trace_export(ctx: int, lat: int) -> int:
+    return _check(load().flame_trace_export(ctx, lat), ctx)
+
+
+def flame_trace_step(ctx: int, src: int, dst: int) -> int:
+    return _check(load().flame_trace_step(ctx, src, dst), ctx)
 
 
 def flame_adjoint_step(ctx: int, state: int, lam_next: int, lam: int, lam_j: int) -> int:

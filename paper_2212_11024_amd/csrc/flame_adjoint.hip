@@ -217,7 +217,7 @@ flame_status flame_step_save(flame_ctx* c, void* state) {
     return FLAME_E_INVAL;
   }
   const SetPtrs ptr = set_ptrs(c);
-  hipError_t e = launch_step(c, ptr, state);
+  hipError_t e = launch_step(c, ptr, c->stride, state);
   if (e != hipSuccess) {
     c->err = std::string("step kernel: ") + hipGetErrorString(e);
     return FLAME_E_HIP;
@@ -227,6 +227,32 @@ flame_status flame_step_save(flame_ctx* c, void* state) {
   if (two_f || two_g) c->cur ^= 1;
   if (!two_f || !two_g) c->parity ^= 1;
   c->steps += 1;
+  return FLAME_OK;
+}
+
+flame_status flame_trace_step(flame_ctx* c, const void* src, void* dst) {
+  if (!c) return FLAME_E_INVAL;
+  if (c->p.jmode != FLAME_J_MOMENT) {
+    c->err = "trace step is available on the moment route only";
+    return FLAME_E_INVAL;
+  }
+  if (!src || !dst || src == dst) {
+    c->err = "trace step needs distinct src and dst";
+    return FLAME_E_INVAL;
+  }
+  const size_t set = 27 * c->n * value_bytes(c->p.storage);
+  SetPtrs s{};
+  s.f_src = const_cast<void*>(src);
+  s.g_src = static_cast<char*>(s.f_src) + set;
+  s.f_dst = dst;
+  s.g_dst = static_cast<char*>(dst) + set;
+  s.fluid_aa = false;
+  s.mag_aa = false;
+  hipError_t e = launch_step(c, s, c->n, nullptr);
+  if (e != hipSuccess) {
+    c->err = std::string("step kernel: ") + hipGetErrorString(e);
+    return FLAME_E_HIP;
+  }
   return FLAME_OK;
 }
 

@@ -38,6 +38,18 @@ struct View {
   __device__ size_t node(int x, int y, int z) const {
     return (static_cast<size_t>(z) * ny + y) * nx + x;
   }
+  // element of F / G holding canonical population i (component c) of node (x, y, z), for the
+  // trace export
+  __device__ size_t fidx(int i, int x, int y, int z) const {
+    return fmode == 0 ? static_cast<size_t>(i) * stride + node(x, y, z)
+                      : static_cast<size_t>(fmode == 1 ? oppq(i) : i) * stride +
+                            node(wrap(x - cq(i, 0), nx), wrap(y - cq(i, 1), ny), wrap(z - cq(i, 2), nz));
+  }
+  __device__ size_t gidx(int i, int c, int x, int y, int z) const {
+    return gmode == 0 ? static_cast<size_t>(i * 3 + c) * stride + node(x, y, z)
+                      : static_cast<size_t>((gmode == 1 ? oppm(i) : i) * 3 + c) * stride +
+                            node(wrap(x - xim(i, 0), nx), wrap(y - xim(i, 1), ny), wrap(z - xim(i, 2), nz));
+  }
   __device__ double f(int i, int x, int y, int z) const {
     size_t idx = fmode == 0 ? static_cast<size_t>(i) * stride + node(x, y, z)
                             : static_cast<size_t>(fmode == 1 ? oppq(i) : i) * stride +
@@ -242,6 +254,24 @@ __global__ __launch_bounds__(256) void set_kernel(S* F, S* G, size_t n, size_t s
       const size_t k = static_cast<size_t>(i * 3 + c);
       G[k * stride + at.g(i, x, y, z)] = E::enc(src[(27 + k) * n + cell] - wm(i) * r.b0[c], E::mscale(i));
     }
+}
+
+// Trace lattice of the current state (two-lattice pull layout, node stride n): canonical
+// population i of node x goes to slot i at x - c_i, where a pull step at x reads it. The stored
+// values are moved without decoding, so the copy is exact.
+template <typename S>
+__global__ __launch_bounds__(256) void export_kernel(View<S> v, S* lat) {
+  const size_t cell = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (cell >= v.n) return;
+  int x, y, z;
+  node_xyz(cell, v.nx, v.ny, x, y, z);
+  for (int i = 0; i < kQ; ++i)
+    lat[static_cast<size_t>(i) * v.n + v.node(wrap(x - cq(i, 0), v.nx), wrap(y - cq(i, 1), v.ny),
+                                              wrap(z - cq(i, 2), v.nz))] = v.F[v.fidx(i, x, y, z)];
+  for (int i = 0; i < 7; ++i) {
+    const size_t dn = v.node(wrap(x - xim(i, 0), v.nx), wrap(y - xim(i, 1), v.ny), wrap(z - xim(i, 2), v.nz));
+    for (int c = 0; c < 3; ++c) lat[static_cast<size_t>(kQ + i * 3 + c) * v.n + dn] = v.G[v.gidx(i, c, x, y, z)];
+  }
 }
 
 template <typename S>
@@ -704,7 +734,7 @@ flame_status flame_step(flame_ctx* c, int64_t nsteps) {
   const bool two_g = mag_two_lattice(c->p);
   for (int64_t s = 0; s < nsteps; ++s) {
     const SetPtrs ptr = set_ptrs(c);
-    hipError_t e = launch_step(c, ptr, nullptr);
+    hipError_t e = launch_step(c, ptr, c->stride, nullptr);
     if (e != hipSuccess) return fail(c, FLAME_E_HIP, std::string("step kernel: ") + hipGetErrorString(e));
     if (two_f || two_g) c->cur ^= 1;
     if (!two_f || !two_g) c->parity ^= 1;
@@ -850,6 +880,23 @@ flame_status flame_gather(flame_ctx* c, const int64_t* cells, int64_t n, double*
     return hipGetLastError();
   });
   if (e != hipSuccess) return fail(c, FLAME_E_HIP, std::string("gather kernel: ") + hipGetErrorString(e));
+  return FLAME_OK;
+}
+
+size_t flame_trace_bytes(const flame_ctx* c) { return c ? 48 * c->n * value_bytes(c->p.storage) : 0; }
+
+flame_status flame_trace_export(flame_ctx* c, void* lat) {
+  if (!c) return FLAME_E_INVAL;
+  if (!lat) return fail(c, FLAME_E_INVAL, "lat is NULL");
+  if (c->p.layout != FLAME_LAYOUT_AA || c->p.jmode != FLAME_J_MOMENT)
+    return fail(c, FLAME_E_INVAL, "trace export is available on the moment route with the AA layout only");
+  hipError_t e = by_storage(c, [&](auto tag) {
+    using S = decltype(tag);
+    hipLaunchKernelGGL(export_kernel<S>, dim3(blocks_for(c->n, 256)), dim3(256), 0, c->stream, make_view<S>(c),
+                       static_cast<S*>(lat));
+    return hipGetLastError();
+  });
+  if (e != hipSuccess) return fail(c, FLAME_E_HIP, std::string("export kernel: ") + hipGetErrorString(e));
   return FLAME_OK;
 }
 

@@ -89,8 +89,9 @@ __device__ __forceinline__ void logical_block(unsigned gx, unsigned gy, unsigned
   bz = l / (gx * gy);
 }
 
-// One fused step; with save != null also writes the pre-collision state of every node
-// (arithmetic type, [48 populations + 3 J][n]).
-hipError_t launch_step(const flame_ctx* c, const SetPtrs& s, void* save);
+// One fused step over the sets s, whose population arrays are stride elements apart; with
+// save != null also writes the pre-collision state of every node (arithmetic type,
+// [48 populations + 3 J][n]).
+hipError_t launch_step(const flame_ctx* c, const SetPtrs& s, size_t stride, void* save);
 
 }  // namespace flame

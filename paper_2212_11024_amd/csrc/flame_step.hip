@@ -386,7 +386,7 @@ __global__ __launch_bounds__(kTX * Tile<typename Enc<S>::R>::ty, FLAME_ZMARCH_WA
 }
 
 template <typename S, bool SAVE>
-static hipError_t launch_typed(const flame_ctx* c, const SetPtrs& s, void* save) {
+static hipError_t launch_typed(const flame_ctx* c, const SetPtrs& s, size_t stride, void* save) {
   using R = typename Enc<S>::R;
   StepArgs<S> a;
   a.f_src = static_cast<const S*>(s.f_src);
@@ -399,7 +399,7 @@ static hipError_t launch_typed(const flame_ctx* c, const SetPtrs& s, void* save)
   a.ny = c->p.ny;
   a.nz = c->p.nz;
   a.n = c->n;
-  a.stride = c->stride;
+  a.stride = stride;
   a.save = static_cast<R*>(save);
   a.k.omega = R(c->omega);
   a.k.omega_b = R(c->omega_b);
@@ -431,11 +431,15 @@ static hipError_t launch_typed(const flame_ctx* c, const SetPtrs& s, void* save)
   return hipGetLastError();
 }
 
-hipError_t launch_step(const flame_ctx* c, const SetPtrs& s, void* save) {
+hipError_t launch_step(const flame_ctx* c, const SetPtrs& s, size_t stride, void* save) {
   switch (c->p.storage) {
-    case FLAME_F64: return save ? launch_typed<double, true>(c, s, save) : launch_typed<double, false>(c, s, save);
-    case FLAME_F32: return save ? launch_typed<float, true>(c, s, save) : launch_typed<float, false>(c, s, save);
-    default: return save ? launch_typed<_Float16, true>(c, s, save) : launch_typed<_Float16, false>(c, s, save);
+    case FLAME_F64:
+      return save ? launch_typed<double, true>(c, s, stride, save) : launch_typed<double, false>(c, s, stride, save);
+    case FLAME_F32:
+      return save ? launch_typed<float, true>(c, s, stride, save) : launch_typed<float, false>(c, s, stride, save);
+    default:
+      return save ? launch_typed<_Float16, true>(c, s, stride, save)
+                  : launch_typed<_Float16, false>(c, s, stride, save);
   }
 }
 
