@@ -3,17 +3,21 @@
 Workload (forced Hall-MHD turbulence, 512^3): periodic 512^3 grid, FP32 populations stored as
 deviations from rest (FP32 collision arithmetic); seeded random-phase solenoidal u and b with a
 flat spectrum in shells 1 <= |k| <= 4, rms u = rms b = 0.02; static solenoidal forcing of u
-and B at 0 < |k| <= 2 with rms 1e-5 each; nu = eta = 0.001; d_i = 4 cells; b0 = 0; J by the
-curl stencil; fluid populations updated in place (AA), magnetic ones double-buffered.
+and B at 0 < |k| <= 2 with rms 1e-5 each; nu = eta = 0.001; d_i = 4 cells; b0 = 0; fluid
+populations updated in place (AA).
 
 One step = one launch of the fused kernel over the whole grid (all of the hot path: loads,
 moments, J, both collisions, streaming stores). The timed region holds exactly --steps steps,
 bracketed by device synchronisation; the inputs are resident in HBM before it starts.
 
-Prints one JSON line. Besides the headline (FP32, stencil J) it reports the same workload with
-the moment-route J and with FP64 storage, the roofline of the headline kernel (algorithmic
-bytes per launch over the event-timed average launch), and the CPU oracle timed on a bounded
-sample on the host cores.
+Prints one JSON line. The headline is the FP32 step with J from the magnetic moments (the
+paper's route), which stays stable on this workload. The variants time the same workload with
+the curl-stencil J (its kernel stages b tiles in LDS; the explicit stencil makes the Hall term
+linearly unstable at these parameters, so its state turns non-finite within about a hundred
+steps, which each variant reports), with d_i = 0 for the stencil kernel, and with FP64 and FP16
+storage. Also reported: the roofline of the headline kernel (algorithmic bytes per launch over
+the event-timed average launch), the reverse-mode cost on the adjoint workload, and the CPU
+oracle timed on a bounded sample on the host cores.
 """
 
 from __future__ import annotations
@@ -31,17 +35,20 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBPS = 8000.0        # MI355X HBM3E peak
 
 # HBM traffic of the headline kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE passes, calibrated on
-# a plain copy (profiles/traffic_step_f32_stencil_512.md). Valid only for the kernel source it was
+# a plain copy (see the traffic summary named below). Valid only for the kernel source it was
 # measured on: reported as null once the fingerprint of the kernel sources changes.
-TRAFFIC_RECORD = {"fingerprint": "e682d944b83d657d", "GB_per_launch": 69.03,
-                  "profile": "profiles/traffic_step_f32_stencil_512.md"}
+TRAFFIC_RECORD = {"fingerprint": "40b12b8e7670ca9e", "GB_per_launch": 55.33,
+                  "profile": "profiles/traffic_step_f32_moment_512.md"}
 
 
 def kernel_fingerprint():
     import hashlib
     csrc = os.path.join(ROOT, "paper_2212_11024_amd", "csrc")
-    data = b"".join(open(os.path.join(csrc, f), "rb").read() for f in ("flame_step.hip", "flame_device.h"))
+    data = b"".join(open(os.path.join(csrc, f), "rb").read()
+                    for f in ("flame_step.hip", "flame_device.h", "flame_internal.h"))
     return hashlib.sha256(data).hexdigest()[:16]
+
+
 WORKLOAD = "forced Hall-MHD turbulence 512^3 (FP32 deviation storage, FP64 reductions)"
 
 
@@ -59,12 +66,12 @@ def workload_fields(n, device):
 PHYS = dict(nu=0.001, eta=0.001, d_i=4.0, b0=(0.0, 0.0, 0.0))
 
 
-def make_solver(n, storage="f32", jmode="stencil", layout="aa", device="cuda", fields=None):
+def make_solver(n, storage="f32", jmode="moment", layout="aa", device="cuda", fields=None, d_i=None):
     import torch
     from paper_2212_11024_amd.solver import Solver
     u, gu, b, gb, fu, fb = fields if fields is not None else workload_fields(n, device)
-    s = Solver(n, n, n, PHYS["nu"], PHYS["eta"], PHYS["d_i"], PHYS["b0"], storage, jmode, layout,
-               u, b, gu, gb, fu, fb, device=device)
+    s = Solver(n, n, n, PHYS["nu"], PHYS["eta"], PHYS["d_i"] if d_i is None else d_i, PHYS["b0"], storage, jmode,
+               layout, u, b, gu, gb, fu, fb, device=device)
     torch.cuda.synchronize()
     return s
 
@@ -77,9 +84,9 @@ def bytes_per_node(storage, forced=True):
     return 2 * 48 * vb + (6 * fb if forced else 0)
 
 
-def time_variant(n, storage, jmode, steps, warmup, fields):
+def time_variant(n, storage, jmode, d_i, steps, warmup, fields):
     import torch
-    s = make_solver(n, storage, jmode, "aa", fields=fields)
+    s = make_solver(n, storage, jmode, "aa", fields=fields, d_i=d_i)
     s.step(warmup)
     torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
@@ -99,11 +106,12 @@ def time_variant(n, storage, jmode, steps, warmup, fields):
     nodes = n ** 3
     bpn = bytes_per_node(storage)
     return {
-        "storage": storage, "jmode": jmode, "ms_per_step": ms, "wall_s": wall,
+        "storage": storage, "jmode": jmode, "d_i": d_i, "ms_per_step": ms, "wall_s": wall,
         "mlups": nodes / (ms * 1e-3) / 1e6,
         "bytes_per_node": bpn,
         "achieved_GBps": bpn * nodes / (ms * 1e-3) / 1e9,
         "E_kin": float(red[0]), "E_mag": float(red[1]), "nonfinite_nodes": int(red[8]),
+        "finite": int(red[8]) == 0,
     }
 
 
@@ -192,13 +200,13 @@ def copy_probe(gib=4, reps=5):
 
 def cpu_baseline(seconds=15.0):
     """The FP64 oracle (closed-form route, as it stands) on a 32^3 sample of the workload's
-    physics, on the host cores; MLUPS = nodes x steps / time."""
+    physics (moment-route J, like the headline), on the host cores; MLUPS = nodes x steps / time."""
     import torch
     from oracle import scheme
     torch.set_num_threads(int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
     n = 32
     u, gu, b, gb, fu, fb = workload_fields(n, "cpu")
-    p = scheme.Params(n, n, n, PHYS["nu"], PHYS["eta"], PHYS["d_i"], PHYS["b0"], "stencil", "closed", fu, fb)
+    p = scheme.Params(n, n, n, PHYS["nu"], PHYS["eta"], PHYS["d_i"], PHYS["b0"], "moment", "closed", fu, fb)
     st = scheme.init_state(p, u, b, gu, gb)
     st = scheme.step(st, p, 1)                  # warm-up
     steps, t0 = 0, time.perf_counter()
@@ -210,7 +218,7 @@ def cpu_baseline(seconds=15.0):
             break
     return {"value": n ** 3 * steps / el / 1e6, "unit": "MLUPS", "cores": torch.get_num_threads(),
             "kind": "oracle",
-            "sample": f"32^3 nodes, {steps} steps of the workload physics (stencil J, forced), "
+            "sample": f"32^3 nodes, {steps} steps of the workload physics (moment J, forced), "
                       f"FP64 closed-form route, {el:.1f} s"}
 
 
@@ -220,7 +228,7 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--size", type=int, default=512)
-    ap.add_argument("--variants", default="all", help="all | headline")
+    ap.add_argument("--variants", default="all", help="all | headline | stencil (the FP32 stencil kernel alone)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-probe", action="store_true",
@@ -241,16 +249,18 @@ def main(argv=None):
     copy = copy_probe() if args.copy_probe else None
     fields = workload_fields(n, "cuda")
     torch.cuda.synchronize()
-    variants = [("f32", "stencil")]
+    d_i = PHYS["d_i"]
+    variants = [("f32", "stencil", d_i)] if args.variants == "stencil" else [("f32", "moment", d_i)]
     if args.variants == "all":
-        variants += [("f32", "moment"), ("f64", "stencil"), ("f16", "stencil")]
+        variants += [("f32", "stencil", d_i), ("f32", "stencil", 0.0), ("f64", "moment", d_i),
+                     ("f64", "stencil", d_i), ("f16", "moment", d_i), ("f16", "stencil", d_i)]
     results = []
-    for storage, jmode in variants:
-        print(f"[bench] {n}^3 {storage} {jmode}: {args.warmup} warm-up + {args.steps} timed steps", file=sys.stderr,
-              flush=True)
-        r = time_variant(n, storage, jmode, args.steps, args.warmup, fields)
-        print(f"[bench]   {r['ms_per_step']:.3f} ms/step, {r['mlups']:.0f} MLUPS, {r['achieved_GBps']:.0f} GB/s",
+    for storage, jmode, di in variants:
+        print(f"[bench] {n}^3 {storage} {jmode} d_i={di}: {args.warmup} warm-up + {args.steps} timed steps",
               file=sys.stderr, flush=True)
+        r = time_variant(n, storage, jmode, di, args.steps, args.warmup, fields)
+        print(f"[bench]   {r['ms_per_step']:.3f} ms/step, {r['mlups']:.0f} MLUPS, {r['achieved_GBps']:.0f} GB/s, "
+              f"non-finite nodes {r['nonfinite_nodes']}", file=sys.stderr, flush=True)
         results.append(r)
     del fields
     torch.cuda.empty_cache()
@@ -262,7 +272,7 @@ def main(argv=None):
             print(f"[bench]   {adj[-1]}", file=sys.stderr, flush=True)
     head = results[0]
     traffic = None
-    if n == 512 and kernel_fingerprint() == TRAFFIC_RECORD["fingerprint"]:
+    if n == 512 and TRAFFIC_RECORD["fingerprint"] and kernel_fingerprint() == TRAFFIC_RECORD["fingerprint"]:
         traffic = TRAFFIC_RECORD["GB_per_launch"]
     cpu = None
     if not args.no_cpu_baseline:
@@ -283,7 +293,7 @@ def main(argv=None):
         "data": "synthetic (seeded Fourier-mode fields)",
         "config": {"workload": WORKLOAD if n == 512 else WORKLOAD.replace("512^3", f"{n}^3"),
                    "grid": [n, n, n], "nu": PHYS["nu"], "eta": PHYS["eta"], "d_i": PHYS["d_i"],
-                   "j_mode": "stencil", "layout": "aa (fluid in place, magnetic double-buffered)",
+                   "j_mode": "moment", "layout": "aa (fluid and magnetic in place)",
                    "forcing": "static, |k| <= 2, rms 1e-5"},
         "roofline": {"bound": "hbm", "achieved": round(head["achieved_GBps"], 1), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(head["achieved_GBps"] / HBM_PEAK_GBPS, 4),
@@ -291,7 +301,7 @@ def main(argv=None):
                      "algorithmic_GB_per_launch": round(head["bytes_per_node"] * n ** 3 / 1e9, 3),
                      "bytes_per_node": head["bytes_per_node"]},
         "variants": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()} for r in results],
-        "adjoint_forward_ratio": (min(a["ratio"] for a in adj) if adj else None),
+        "adjoint_forward_ratio": (adj[0]["ratio"] if adj else None),
         "adjoint": adj,
         "copy_probe": copy,
         "cpu_baseline": cpu,
