@@ -100,6 +100,7 @@ def time_variant(n, storage, jmode, d_i, steps, warmup, fields):
     wall = time.perf_counter() - t0
     ms = start.elapsed_time(end) / steps
     red = s.reduce(allow_nonfinite=True)
+    spectra = {f: s.spectrum(f, NSHELLS) for f in ("u", "B")}
     s.close()
     del s
     torch.cuda.empty_cache()
@@ -112,7 +113,27 @@ def time_variant(n, storage, jmode, d_i, steps, warmup, fields):
         "achieved_GBps": bpn * nodes / (ms * 1e-3) / 1e9,
         "E_kin": float(red[0]), "E_mag": float(red[1]), "nonfinite_nodes": int(red[8]),
         "finite": int(red[8]) == 0,
+        "_spectra": spectra,
     }
+
+
+NSHELLS = 33          # shell spectra 0..32 recorded after each timed run
+
+
+def spectral_error(spec, ref):
+    """FP32 / FP16 run against the FP64 run of the same workload after the same steps, for u and
+    B (FP64 shell spectra of each run's node fields): the largest relative error over the
+    energetic shells 1..8 (the initial shells 1..4, the forcing and the first cascade), and the
+    energy-weighted error sum|dE| / sum E over shells 1..32. Higher shells hold energies near the
+    FP64 run's own rounding floor, so their relative errors measure noise, not accuracy."""
+    out = {}
+    for f in ("u", "B"):
+        a, r = [float(x) for x in spec[f]], [float(x) for x in ref[f]]
+        rel = [abs(a[k] - r[k]) / r[k] for k in range(1, 9)]
+        w = sum(abs(a[k] - r[k]) for k in range(1, NSHELLS)) / sum(r[k] for k in range(1, NSHELLS))
+        out[f] = {"max_rel_shells_1_8": max(rel) if all(math.isfinite(x) for x in rel) else math.nan,
+                  "weighted_shells_1_32": w}
+    return out
 
 
 ADJ_PHYS = dict(nu=0.002, eta=0.002, d_i=4.0, b0=(0.0, 0.0, 0.0))
@@ -231,8 +252,9 @@ def main(argv=None):
     ap.add_argument("--variants", default="all", help="all | headline | stencil (the FP32 stencil kernel alone)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--copy-probe", action="store_true",
-                    help="also time a plain 4 GiB device copy (bandwidth reference and counter calibration)")
+    ap.add_argument("--no-copy-probe", action="store_true",
+                    help="skip the plain 4 GiB device copy (bandwidth reference and counter calibration)")
+    ap.add_argument("--copy-probe", action="store_true", help="time the copy also with --variants headline/stencil")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU slab "
@@ -246,7 +268,7 @@ def main(argv=None):
         build()
     torch.cuda.set_device(0)
     n = args.size
-    copy = copy_probe() if args.copy_probe else None
+    copy = copy_probe() if (args.copy_probe or (args.variants == "all" and not args.no_copy_probe)) else None
     fields = workload_fields(n, "cuda")
     torch.cuda.synchronize()
     d_i = PHYS["d_i"]
@@ -264,6 +286,14 @@ def main(argv=None):
         results.append(r)
     del fields
     torch.cuda.empty_cache()
+    ref = {(r["jmode"], r["d_i"]): r["_spectra"] for r in results if r["storage"] == "f64"}
+    for r in results:
+        sp = r.pop("_spectra")
+        key = (r["jmode"], r["d_i"])
+        if r["storage"] != "f64" and key in ref:
+            err = spectral_error(sp, ref[key])
+            r["spectral_error_vs_f64"] = {f: {k: (round(v, 8) if math.isfinite(v) else None) for k, v in e.items()}
+                                          for f, e in err.items()}
     adj = []
     if args.variants == "all":
         for jm in ("moment", "stencil"):
@@ -299,8 +329,10 @@ def main(argv=None):
                      "unit": "GB/s", "frac": round(head["achieved_GBps"] / HBM_PEAK_GBPS, 4),
                      "traffic": traffic, "traffic_unit": "GB per launch (measured HBM bytes)",
                      "algorithmic_GB_per_launch": round(head["bytes_per_node"] * n ** 3 / 1e9, 3),
-                     "bytes_per_node": head["bytes_per_node"]},
-        "variants": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()} for r in results],
+                     "bytes_per_node": head["bytes_per_node"],
+                     "copy_GBps_same_box": copy["GBps"] if copy else None,
+                     "frac_of_copy": round(head["achieved_GBps"] / copy["GBps"], 4) if copy else None},
+        "variants": [{k: (float(f"{v:.6g}") if isinstance(v, float) else v) for k, v in r.items()} for r in results],
         "adjoint_forward_ratio": (adj[0]["ratio"] if adj else None),
         "adjoint": adj,
         "copy_probe": copy,

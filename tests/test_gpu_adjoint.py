@@ -7,7 +7,6 @@ both J routes, forced, with checkpointed segments."""
 
 import math
 
-import numpy as np
 import pytest
 import torch
 
@@ -54,16 +53,16 @@ def _gpu_loss(u, b, cfg, target, nshells):
 
 @pytest.mark.parametrize("jmode", ["moment", "stencil"])
 def test_adjoint_matches_central_differences(jmode):
-    n, steps, ckpt, nshells = 10, 24, 8, 6
+    """16 seeded solenoidal directions (shells 1..5, unit rms), step 1e-4 of the field rms."""
+    n, steps, ckpt, nshells = 12, 24, 8, 6
     print(f"[adjoint] FD {jmode}", flush=True)
     u, b, fu, fb = _fields(n)
     cfg = _cfg(n, jmode, "f64", steps, ckpt, fu, fb)
     target = torch.linspace(1e-5, 2e-6, nshells, dtype=torch.float64)
     loss, gu, gb = _gpu_grad(u, b, cfg, target, nshells)
-    rng = np.random.default_rng(7)
-    for j in range(4):
-        du, _ = synthetic.evaluate(synthetic.shell_field(100 + j, 1, 3, 1.0), (n, n, n), gradient=False)
-        db, _ = synthetic.evaluate(synthetic.shell_field(200 + j, 1, 3, 1.0), (n, n, n), gradient=False)
+    for j in range(16):
+        du, _ = synthetic.evaluate(synthetic.shell_field(100 + j, 1, 5, 1.0), (n, n, n), gradient=False)
+        db, _ = synthetic.evaluate(synthetic.shell_field(200 + j, 1, 5, 1.0), (n, n, n), gradient=False)
         eps = 1e-4 * 0.02
         lp = _gpu_loss(u + eps * du, b + eps * db, cfg, target, nshells)
         lm = _gpu_loss(u - eps * du, b - eps * db, cfg, target, nshells)
@@ -72,7 +71,6 @@ def test_adjoint_matches_central_differences(jmode):
         print(f"[adjoint] {jmode} direction {j}: adjoint {ad:.10e} fd {fd:.10e} rel {abs(ad - fd) / abs(fd):.2e}",
               flush=True)
         assert abs(ad - fd) <= 1e-6 * abs(fd)
-    del rng
 
 
 def _oracle_grad(u, b, cfg, target, nshells):
@@ -110,11 +108,12 @@ def _oracle_grad(u, b, cfg, target, nshells):
 
 @pytest.mark.parametrize("jmode", ["moment", "stencil"])
 def test_adjoint_matches_oracle_autograd(jmode):
-    n, steps, ckpt, nshells = 6, 7, 3, 4
+    """16^3, 50 steps in checkpoint segments of 10, forced, both J routes."""
+    n, steps, ckpt, nshells = 16, 50, 10, 8
     print(f"[adjoint] oracle {jmode}", flush=True)
     u, b, fu, fb = _fields(n, seed=3)
     cfg = _cfg(n, jmode, "f64", steps, ckpt, fu, fb)
-    target = torch.tensor([0.0, 1e-5, 5e-6, 1e-6], dtype=torch.float64)
+    target = torch.linspace(1e-5, 2e-6, nshells, dtype=torch.float64)
     _, gu, gb = _gpu_grad(u, b, cfg, target, nshells)
     ou, ob = _oracle_grad(u, b, cfg, target, nshells)
     rel = float(torch.sqrt(((gu - ou) ** 2).sum() + ((gb - ob) ** 2).sum()) /
