@@ -139,11 +139,12 @@ def spectral_error(spec, ref):
 ADJ_PHYS = dict(nu=0.002, eta=0.002, d_i=4.0, b0=(0.0, 0.0, 0.0))
 
 
-def adjoint_timing(n=128, storage="f32", jmode="moment", seg=50):
+def adjoint_timing(n=128, storage="f32", jmode="moment", seg=50, recompute="state"):
     """Cost of reverse mode on the adjoint workload (n^3, decaying-turbulence fields, nu = eta =
-    0.002, d_i = 4): one checkpoint segment of the backward sweep (restore, seg state-saving
-    steps, seg adjoint steps) against seg forward steps. The segment is swept once untimed first,
-    so that every buffer has been touched before the timed sweep."""
+    0.002, d_i = 4): one checkpoint segment of the backward sweep against seg forward steps.
+    recompute = "state": restore the checkpoint, seg state-saving steps, seg adjoint steps;
+    "trace" (moment route): seg - 1 trace steps from the checkpoint lattice, seg trace adjoint
+    steps. The segment is swept once untimed first, so that every buffer has been touched."""
     import torch
     import synthetic
     from paper_2212_11024_amd import _lib as L
@@ -157,27 +158,45 @@ def adjoint_timing(n=128, storage="f32", jmode="moment", seg=50):
     adt = torch.float64 if storage == "f64" else torch.float32
     ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
     s.step(5)
-    ckf, ckg = s.get_populations(deviations=True)
-    ckf, ckg = ckf.clone(), ckg.clone()
-    states = torch.empty((seg, 51 * s.n), dtype=adt, device="cuda")
     lam = torch.zeros(48 * s.n, dtype=adt, device="cuda")
     lam2 = torch.empty_like(lam)
-    lam_j = torch.empty(3 * s.n, dtype=adt, device="cuda")
+    if recompute == "trace":
+        chain = torch.empty((seg, L.flame_trace_bytes(s.ctx)), dtype=torch.uint8, device="cuda")
+        L.flame_trace_export(s.ctx, chain[0].data_ptr())
 
-    def segment(lam, lam2):
-        s.set_populations(ckf, ckg, deviations=True)
-        for k in range(seg):
-            L.flame_step_save(s.ctx, states[k].data_ptr())
-        mid = ev()
-        mid.record()
-        for k in reversed(range(seg)):
-            L.flame_adjoint_step(s.ctx, states[k].data_ptr(), lam.data_ptr(), lam2.data_ptr(), lam_j.data_ptr())
-            lam, lam2 = lam2, lam
-        return mid
+        def segment(lam, lam2):
+            for k in range(seg - 1):
+                L.flame_trace_step(s.ctx, chain[k].data_ptr(), chain[k + 1].data_ptr())
+            mid = ev()
+            mid.record()
+            for k in reversed(range(seg)):
+                L.flame_adjoint_trace_step(s.ctx, chain[k].data_ptr(), lam.data_ptr(), lam2.data_ptr())
+                lam, lam2 = lam2, lam
+            return mid
+        buffers = [chain]
+    else:
+        ckf, ckg = s.get_populations(deviations=True)
+        ckf, ckg = ckf.clone(), ckg.clone()
+        states = torch.empty((seg, 51 * s.n), dtype=adt, device="cuda")
+        lam_j = torch.empty(3 * s.n, dtype=adt, device="cuda")
+
+        def segment(lam, lam2):
+            s.set_populations(ckf, ckg, deviations=True)
+            for k in range(seg):
+                L.flame_step_save(s.ctx, states[k].data_ptr())
+            mid = ev()
+            mid.record()
+            for k in reversed(range(seg)):
+                L.flame_adjoint_step(s.ctx, states[k].data_ptr(), lam.data_ptr(), lam2.data_ptr(),
+                                     lam_j.data_ptr())
+                lam, lam2 = lam2, lam
+            return mid
+        buffers = [states, lam_j, ckf, ckg]
 
     segment(lam, lam2)
     lam.zero_()
-    s.set_populations(ckf, ckg, deviations=True)
+    if recompute != "trace":
+        s.set_populations(ckf, ckg, deviations=True)
     torch.cuda.synchronize()
     e0, e1 = ev(), ev()
     e0.record()
@@ -192,9 +211,9 @@ def adjoint_timing(n=128, storage="f32", jmode="moment", seg=50):
     torch.cuda.synchronize()
     t_rec, t_adj = e0.elapsed_time(e1), e1.elapsed_time(e2)
     s.close()
-    del states, lam, lam2, lam_j, s
+    del buffers, lam, lam2, s
     torch.cuda.empty_cache()
-    return {"grid": [n, n, n], "storage": storage, "jmode": jmode, "segment_steps": seg,
+    return {"grid": [n, n, n], "storage": storage, "jmode": jmode, "recompute": recompute, "segment_steps": seg,
             "forward_ms_per_step": round(t_fwd / seg, 4), "recompute_ms_per_step": round(t_rec / seg, 4),
             "adjoint_ms_per_step": round(t_adj / seg, 4), "ratio": round((t_rec + t_adj) / t_fwd, 3)}
 
@@ -296,9 +315,9 @@ def main(argv=None):
                                           for f, e in err.items()}
     adj = []
     if args.variants == "all":
-        for jm in ("moment", "stencil"):
-            print(f"[bench] adjoint segment 128^3 f32 {jm}", file=sys.stderr, flush=True)
-            adj.append(adjoint_timing(128, "f32", jm))
+        for jm, rc in (("moment", "trace"), ("moment", "state"), ("stencil", "state")):
+            print(f"[bench] adjoint segment 128^3 f32 {jm} ({rc} recompute)", file=sys.stderr, flush=True)
+            adj.append(adjoint_timing(128, "f32", jm, recompute=rc))
             print(f"[bench]   {adj[-1]}", file=sys.stderr, flush=True)
     head = results[0]
     traffic = None

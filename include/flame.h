@@ -187,6 +187,12 @@ size_t flame_trace_bytes(const flame_ctx* c);
 flame_status flame_trace_export(flame_ctx* c, void* lat);
 flame_status flame_trace_step(flame_ctx* c, const void* src, void* dst);
 
+/* Moment route: lam = (d step / d x)^T lam_next for the step whose pre-collision state is the
+ * trace lattice src pulled (the step flame_trace_step takes from src), with J recomputed from
+ * that state; the same reverse pass as flame_adjoint_step without a saved state. lam, lam_next
+ * as for flame_adjoint_step; lam must not alias lam_next. */
+flame_status flame_adjoint_trace_step(flame_ctx* c, const void* src, const void* lam_next, void* lam);
+
 /* lam = adjoint of the current state for a loss of its node fields: dl_du, dl_db (device
  * double [3][n], nullable = zero) are d loss / du and d loss / dB with u, B as flame_moments
  * returns them. */

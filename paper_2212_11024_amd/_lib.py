@@ -55,6 +55,7 @@ _SIGNATURES = {
     "flame_trace_bytes": (ctypes.c_size_t, [_P]),
     "flame_trace_export": (ctypes.c_int32, [_P, _P]),
     "flame_trace_step": (ctypes.c_int32, [_P, _P, _P]),
+    "flame_adjoint_trace_step": (ctypes.c_int32, [_P, _P, _P, _P]),
     "flame_adjoint_step": (ctypes.c_int32, [_P, _P, _P, _P, _P]),
     "flame_adjoint_fields": (ctypes.c_int32, [_P, _P, _P, _P]),
     "flame_adjoint_init": (ctypes.c_int32, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
@@ -168,6 +169,10 @@ def flame_trace_export(ctx: int, lat: int) -> int:
 
 def flame_trace_step(ctx: int, src: int, dst: int) -> int:
     return _check(load().flame_trace_step(ctx, src, dst), ctx)
+
+
+def flame_adjoint_trace_step(ctx: int, src: int, lam_next: int, lam: int) -> int:
+    return _check(load().flame_adjoint_trace_step(ctx, src, lam_next, lam), ctx)
 
 
 def flame_adjoint_step(ctx: int, state: int, lam_next: int, lam: int, lam_j: int) -> int:

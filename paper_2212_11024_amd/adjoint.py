@@ -2,11 +2,17 @@
 
 ``FlameRollout`` is a ``torch.autograd.Function``: forward initialises a run from (u0, b0,
 grad u0, grad b0) and advances it ``nsteps`` steps, returning the final node fields (u_T, B_T);
-backward runs the library's hand-written adjoint. Memory is bounded by checkpointing: the forward
-keeps the exact (deviation) state every ``ckpt`` steps; the backward restores each checkpoint,
-recomputes its segment with ``flame_step_save`` (which also records each step's pre-collision
-state) and sweeps the adjoint steps back through it, then applies the adjoint of the initial
-state. All arithmetic is in libflame.so; this module moves pointers.
+backward runs the library's hand-written adjoint. Memory is bounded by checkpointing every
+``ckpt`` steps, and the backward recomputes one segment at a time:
+  * trace recompute (moment route, AA layout): checkpoints are exact trace lattices
+    (``flame_trace_export``); a segment is recomputed as a chain of trace lattices
+    (``flame_trace_step``, one ordinary step each) and swept back with
+    ``flame_adjoint_trace_step``, which pulls each step's state from the chain;
+  * state recompute (any route): checkpoints are the exact deviation state; a segment is
+    recomputed with ``flame_step_save``, which also records each step's pre-collision state and
+    J, and swept back with ``flame_adjoint_step``.
+Then the adjoint of the initial state is applied. All arithmetic is in libflame.so; this module
+moves pointers.
 """
 
 from __future__ import annotations
@@ -76,6 +82,13 @@ class RolloutConfig:
     ckpt: int = 50
     force_u: Optional[torch.Tensor] = None
     force_b: Optional[torch.Tensor] = None
+    recompute: str = "auto"    # "trace" | "state" | "auto" (trace where available)
+
+    def uses_trace(self):
+        available = self.jmode == "moment" and self.layout == "aa"
+        if self.recompute == "trace" and not available:
+            raise ValueError("trace recompute needs the moment route and the AA layout")
+        return available and self.recompute != "state"
 
 
 class FlameRollout(torch.autograd.Function):
@@ -87,11 +100,17 @@ class FlameRollout(torch.autograd.Function):
         s = Solver(cfg.nx, cfg.ny, cfg.nz, cfg.nu, cfg.eta, cfg.d_i, cfg.b0, cfg.storage, cfg.jmode, cfg.layout,
                    u0.detach(), b0.detach(), None if gu0 is None else gu0.detach(),
                    None if gb0 is None else gb0.detach(), cfg.force_u, cfg.force_b)
+        trace = cfg.uses_trace()
         ckpts = []
         done = 0
         while done < cfg.nsteps:
-            f, g = s.get_populations(deviations=True)
-            ckpts.append((f.clone(), g.clone(), done))
+            if trace:
+                lat = torch.empty(L.flame_trace_bytes(s.ctx), dtype=torch.uint8, device=s.device)
+                L.flame_trace_export(s.ctx, lat.data_ptr())
+                ckpts.append((lat, done))
+            else:
+                f, g = s.get_populations(deviations=True)
+                ckpts.append(((f.clone(), g.clone()), done))
             k = min(cfg.ckpt, cfg.nsteps - done)
             s.step(k)
             done += k
@@ -120,15 +139,27 @@ class FlameRollout(torch.autograd.Function):
         gu = None if g_u is None else g_u.to(dev, torch.float64).contiguous()
         gB = None if g_B is None else g_B.to(dev, torch.float64).contiguous()
         L.flame_adjoint_fields(s.ctx, ptr(gu), ptr(gB), lam.data_ptr())
-        states = torch.empty((min(cfg.ckpt, cfg.nsteps), 51 * n), dtype=adt, device=dev)
-        for f, g, start in reversed(ctx.ckpts):
-            length = min(cfg.ckpt, cfg.nsteps - start)
-            s.set_populations(f, g, deviations=True)
-            for k in range(length):
-                L.flame_step_save(s.ctx, states[k].data_ptr())
-            for k in reversed(range(length)):
-                L.flame_adjoint_step(s.ctx, states[k].data_ptr(), lam.data_ptr(), lam2.data_ptr(), ptr(lam_j))
-                lam, lam2 = lam2, lam
+        seg = min(cfg.ckpt, cfg.nsteps)
+        if cfg.uses_trace():
+            pool = torch.empty((max(seg - 1, 0), L.flame_trace_bytes(s.ctx)), dtype=torch.uint8, device=dev)
+            for lat0, start in reversed(ctx.ckpts):
+                length = min(cfg.ckpt, cfg.nsteps - start)
+                chain = [lat0] + [pool[k] for k in range(length - 1)]
+                for k in range(length - 1):
+                    L.flame_trace_step(s.ctx, chain[k].data_ptr(), chain[k + 1].data_ptr())
+                for k in reversed(range(length)):
+                    L.flame_adjoint_trace_step(s.ctx, chain[k].data_ptr(), lam.data_ptr(), lam2.data_ptr())
+                    lam, lam2 = lam2, lam
+        else:
+            states = torch.empty((seg, 51 * n), dtype=adt, device=dev)
+            for (f, g), start in reversed(ctx.ckpts):
+                length = min(cfg.ckpt, cfg.nsteps - start)
+                s.set_populations(f, g, deviations=True)
+                for k in range(length):
+                    L.flame_step_save(s.ctx, states[k].data_ptr())
+                for k in reversed(range(length)):
+                    L.flame_adjoint_step(s.ctx, states[k].data_ptr(), lam.data_ptr(), lam2.data_ptr(), ptr(lam_j))
+                    lam, lam2 = lam2, lam
         out_u = torch.empty_like(u0)
         out_b = torch.empty_like(b0)
         out_gu = None if gu0 is None else torch.empty_like(gu0)

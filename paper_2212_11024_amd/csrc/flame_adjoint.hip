@@ -5,8 +5,11 @@
 // the post-collision population q at node y is lam_{t+1}[q] at y + c_q. The collision is
 // node-local except, on the stencil route, through J = curl b, which couples a node to the field
 // of its six face neighbours; that coupling is transposed in a second pass (the central-difference
-// curl is its own transpose). Forward values are taken from the state saved by the forward step
-// (flame_step_save), so the adjoint reads 51 values, gathers 48 and writes 48 per node.
+// curl is its own transpose). Forward values are taken either from the state saved by the
+// forward step (flame_step_save: the adjoint reads 51 values, gathers 48 and writes 48 per node)
+// or, on the moment route, from a trace lattice (flame_adjoint_trace_step: the pre-collision
+// state is pulled from the previous time level exactly as the forward step pulls it, and J is
+// recomputed from it, so the recompute is one ordinary step and writes nothing extra).
 
 #include "flame_internal.h"
 
@@ -34,8 +37,8 @@ __device__ __forceinline__ size_t anode(int x, int y, int z, int nx, int ny) {
 template <typename R, bool MOMENT>
 __global__ __launch_bounds__(kAdjThreads) void adjoint_step_kernel(AdjArgs<R> a) {
   unsigned bx, by, bz;
-  logical_block((a.nx + kAdjThreads - 1) / kAdjThreads, a.ny, a.nz, bx, by, bz);
-  const int x = bx * kAdjThreads + threadIdx.x, y = by, z = bz;
+  logical_block((a.nx + blockDim.x - 1) / blockDim.x, a.ny, a.nz, bx, by, bz);
+  const int x = bx * blockDim.x + threadIdx.x, y = by, z = bz;
   if (x >= a.nx) return;
   const int nx = a.nx, ny = a.ny, nz = a.nz;
   const size_t n = a.n;
@@ -73,14 +76,90 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_step_kernel(AdjArgs<R> a)
   }
 }
 
+// Moment route from a trace lattice: the step's pre-collision state is the lattice pulled.
+template <typename S>
+struct AdjTraceArgs {
+  using R = typename Enc<S>::R;
+  const S* src;        // trace lattice [48][n] (storage encoding)
+  const R* lam_next;   // [48][n]
+  R* lam;              // [48][n]
+  const R* force_u;
+  const R* force_b;
+  int nx, ny, nz;
+  size_t n;
+  PhysConst<R> k;
+};
+
+template <typename S>
+__global__ __launch_bounds__(kAdjThreads) void adjoint_trace_kernel(AdjTraceArgs<S> a) {
+  using E = Enc<S>;
+  using R = typename E::R;
+  unsigned bx, by, bz;
+  logical_block((a.nx + blockDim.x - 1) / blockDim.x, a.ny, a.nz, bx, by, bz);
+  const int x = bx * blockDim.x + threadIdx.x, y = by, z = bz;
+  if (x >= a.nx) return;
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  const size_t n = a.n;
+  const size_t cell = anode(x, y, z, nx, ny);
+  R f[kQ], g[kM], F[3], Sb[3];
+#pragma unroll
+  for (int i = 0; i < kQ; ++i)
+    f[i] = E::dec(a.src[static_cast<size_t>(i) * n +
+                        anode(wrap(x - cq(i, 0), nx), wrap(y - cq(i, 1), ny), wrap(z - cq(i, 2), nz), nx, ny)],
+                  R(1.0 / E::fscale(i)));
+#pragma unroll
+  for (int i = 0; i < 7; ++i) {
+    const size_t sn = anode(wrap(x - xim(i, 0), nx), wrap(y - xim(i, 1), ny), wrap(z - xim(i, 2), nz), nx, ny);
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      g[i * 3 + c] = E::dec(a.src[static_cast<size_t>(kQ + i * 3 + c) * n + sn], R(1.0 / E::mscale(i)));
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    F[c] = a.force_u ? a.force_u[static_cast<size_t>(c) * n + cell] : R(0);
+    Sb[c] = a.force_b ? a.force_b[static_cast<size_t>(c) * n + cell] : R(0);
+  }
+  // the forward step's J, in its order of operations
+  R J[3];
+  {
+    const FluidMoments<R> m = fluid_moments(f);
+    const R inv_rho = R(1) / (R(1) + m.drho);
+    const R U[3] = {(m.jx + R(0.5) * F[0]) * inv_rho, (m.jy + R(0.5) * F[1]) * inv_rho,
+                    (m.jz + R(0.5) * F[2]) * inv_rho};
+    R b[3], lam[3][3];
+    magnetic_moments(g, b, lam);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) b[c] = b_component(g, c, R(0.5) * Sb[c]);
+    const R B[3] = {a.k.b0[0] + b[0], a.k.b0[1] + b[1], a.k.b0[2] + b[2]};
+    current_from_moments(lam, U, B, a.k.alpha, a.k.omega_b, J);
+  }
+  R mf[kQ], mg[kM];
+#pragma unroll
+  for (int i = 0; i < kQ; ++i)
+    mf[i] = a.lam_next[static_cast<size_t>(i) * n +
+                       anode(wrap(x + cq(i, 0), nx), wrap(y + cq(i, 1), ny), wrap(z + cq(i, 2), nz), nx, ny)];
+#pragma unroll
+  for (int i = 0; i < 7; ++i) {
+    const size_t dn = anode(wrap(x + xim(i, 0), nx), wrap(y + xim(i, 1), ny), wrap(z + xim(i, 2), nz), nx, ny);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) mg[i * 3 + c] = a.lam_next[static_cast<size_t>(kQ + i * 3 + c) * n + dn];
+  }
+  R lf[kQ], lg[kM], lJ[3];
+  collide_vjp<R, true>(f, g, F, Sb, J, a.k, mf, mg, lf, lg, lJ);
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) a.lam[static_cast<size_t>(q) * n + cell] = lf[q];
+#pragma unroll
+  for (int q = 0; q < kM; ++q) a.lam[static_cast<size_t>(kQ + q) * n + cell] = lg[q];
+}
+
 // Stencil route: b_c of every magnetic population set feeds J of the six face neighbours; add
 // curl(lam_J) (the transpose of the central-difference curl) to the adjoint of all 7 g_{i,c}.
 template <typename R>
 __global__ __launch_bounds__(kAdjThreads) void adjoint_curl_kernel(R* lam, const R* lam_j, int nx, int ny, int nz,
                                                                     size_t n) {
   unsigned bx, by, bz;
-  logical_block((nx + kAdjThreads - 1) / kAdjThreads, ny, nz, bx, by, bz);
-  const int x = bx * kAdjThreads + threadIdx.x, y = by, z = bz;
+  logical_block((nx + blockDim.x - 1) / blockDim.x, ny, nz, bx, by, bz);
+  const int x = bx * blockDim.x + threadIdx.x, y = by, z = bz;
   if (x >= nx) return;
   const size_t cell = anode(x, y, z, nx, ny);
   auto L = [&](int c, int dx, int dy, int dz) {
@@ -164,16 +243,40 @@ static hipError_t adjoint_typed(const flame_ctx* c, const void* state, const voi
   a.k.omega_b = R(c->omega_b);
   a.k.alpha = R(c->p.d_i);
   for (int i = 0; i < 3; ++i) a.k.b0[i] = R(c->p.b0[i]);
-  const dim3 grid(((c->p.nx + kAdjThreads - 1) / kAdjThreads) * c->p.ny * c->p.nz);
+  const unsigned tx = row_threads(c->p.nx);
+  const dim3 grid(((c->p.nx + tx - 1) / tx) * c->p.ny * c->p.nz);
   if (c->p.jmode == FLAME_J_STENCIL) {
-    hipLaunchKernelGGL((adjoint_step_kernel<R, false>), grid, dim3(kAdjThreads), 0, c->stream, a);
+    hipLaunchKernelGGL((adjoint_step_kernel<R, false>), grid, dim3(tx), 0, c->stream, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(adjoint_curl_kernel<R>, grid, dim3(kAdjThreads), 0, c->stream, a.lam, a.lam_j, a.nx, a.ny,
+    hipLaunchKernelGGL(adjoint_curl_kernel<R>, grid, dim3(tx), 0, c->stream, a.lam, a.lam_j, a.nx, a.ny,
                        a.nz, a.n);
   } else {
-    hipLaunchKernelGGL((adjoint_step_kernel<R, true>), grid, dim3(kAdjThreads), 0, c->stream, a);
+    hipLaunchKernelGGL((adjoint_step_kernel<R, true>), grid, dim3(tx), 0, c->stream, a);
   }
+  return hipGetLastError();
+}
+
+template <typename S>
+static hipError_t adjoint_trace_typed(const flame_ctx* c, const void* src, const void* lam_next, void* lam) {
+  using R = typename Enc<S>::R;
+  AdjTraceArgs<S> a;
+  a.src = static_cast<const S*>(src);
+  a.lam_next = static_cast<const R*>(lam_next);
+  a.lam = static_cast<R*>(lam);
+  a.force_u = static_cast<const R*>(c->p.force_u);
+  a.force_b = static_cast<const R*>(c->p.force_b);
+  a.nx = c->p.nx;
+  a.ny = c->p.ny;
+  a.nz = c->p.nz;
+  a.n = c->n;
+  a.k.omega = R(c->omega);
+  a.k.omega_b = R(c->omega_b);
+  a.k.alpha = R(c->p.d_i);
+  for (int i = 0; i < 3; ++i) a.k.b0[i] = R(c->p.b0[i]);
+  const unsigned tx = row_threads(a.nx);
+  const dim3 grid(((a.nx + tx - 1) / tx) * a.ny * a.nz);
+  hipLaunchKernelGGL(adjoint_trace_kernel<S>, grid, dim3(tx), 0, c->stream, a);
   return hipGetLastError();
 }
 
@@ -264,6 +367,29 @@ flame_status flame_adjoint_step(flame_ctx* c, const void* state, const void* lam
   }
   hipError_t e = c->p.storage == FLAME_F64 ? adjoint_typed<double>(c, state, lam_next, lam, lam_j)
                                            : adjoint_typed<float>(c, state, lam_next, lam, lam_j);
+  if (e != hipSuccess) {
+    c->err = std::string("adjoint kernel: ") + hipGetErrorString(e);
+    return FLAME_E_HIP;
+  }
+  return FLAME_OK;
+}
+
+flame_status flame_adjoint_trace_step(flame_ctx* c, const void* src, const void* lam_next, void* lam) {
+  if (!c) return FLAME_E_INVAL;
+  if (c->p.jmode != FLAME_J_MOMENT) {
+    c->err = "the trace adjoint is available on the moment route only";
+    return FLAME_E_INVAL;
+  }
+  if (!src || !lam_next || !lam || lam == lam_next) {
+    c->err = "trace adjoint needs src, lam_next and a distinct lam";
+    return FLAME_E_INVAL;
+  }
+  hipError_t e;
+  switch (c->p.storage) {
+    case FLAME_F64: e = adjoint_trace_typed<double>(c, src, lam_next, lam); break;
+    case FLAME_F32: e = adjoint_trace_typed<float>(c, src, lam_next, lam); break;
+    default: e = adjoint_trace_typed<_Float16>(c, src, lam_next, lam); break;
+  }
   if (e != hipSuccess) {
     c->err = std::string("adjoint kernel: ") + hipGetErrorString(e);
     return FLAME_E_HIP;

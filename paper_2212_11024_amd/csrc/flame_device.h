@@ -139,6 +139,17 @@ FLAME_HD void magnetic_moments(const R (&g)[kM], R (&b)[3], R (&lam)[3][3]) {
     for (int c = 0; c < 3; ++c) lam[a][c] = g[(4 + a) * 3 + c] - g[(1 + a) * 3 + c];
 }
 
+// Field fluctuation component c of a node from its magnetic populations, with the source
+// half-shift; one fixed summation order everywhere so a node's b is bitwise the same
+// whichever thread computes it.
+template <typename R>
+FLAME_HD R b_component(const R (&g)[kM], int c, R half_src) {
+  R s = g[c];
+#pragma unroll
+  for (int i = 1; i < 7; ++i) s += g[i * 3 + c];
+  return s + half_src;
+}
+
 // J from the magnetic first moment (Sec. 3.2): (I + 2 alpha w_B / C^2 M(B)) J = -(w_B/C^2) J0,
 // M(B) J = J x B, J0 = eps:Lambda - 2 U x B. Written as J + k (J x B) = r, whose solution is
 // J = (r - k r x B + k^2 (r . B) B) / (1 + k^2 |B|^2), with k = 8 alpha w_B and r = -4 w_B J0.

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <hipfft/hipfft.h>
 
+#include <algorithm>
 #include <string>
 
 #include "../../include/flame.h"
@@ -88,6 +89,11 @@ __device__ __forceinline__ void logical_block(unsigned gx, unsigned gy, unsigned
   by = (l / gx) % gy;
   bz = l / (gx * gy);
 }
+
+// Threads of a row block of the node-local kernels: one row of nx nodes rounded up to whole
+// wavefronts, at most 256 (longer rows take several blocks), so that short rows leave no wave
+// of a block idle.
+inline unsigned row_threads(int nx) { return static_cast<unsigned>(std::min(256, (nx + 63) / 64 * 64)); }
 
 // One fused step over the sets s, whose population arrays are stride elements apart; with
 // save != null also writes the pre-collision state of every node (arithmetic type,

@@ -12,7 +12,8 @@
 // neighbour fields read for curl B are never overwritten during the step.
 //
 // Two kernels:
-//   step_local  - moment-route J: every node independent, one node per thread, 256-wide rows.
+//   step_local  - moment-route J: every node independent, one node per thread, rows of up to
+//     256 nodes per block.
 //   step_zmarch - stencil J: a workgroup owns a 64 x 4 tile of (x, y) and marches along z. It
 //     keeps the field fluctuation b of three consecutive planes in LDS (computed once per node
 //     from that node's own magnetic populations, which it holds in registers for the next
@@ -152,17 +153,6 @@ __device__ __forceinline__ void store_magnetic(const StepArgs<S>& a, const Rows&
   }
 }
 
-// Field fluctuation component c of a node from its magnetic populations, with the source
-// half-shift; one fixed summation order everywhere so a node's b is bitwise the same
-// whichever thread computes it.
-template <typename R>
-__device__ __forceinline__ R b_component(const R (&g)[kM], int c, R half_src) {
-  R s = g[c];
-#pragma unroll
-  for (int i = 1; i < 7; ++i) s += g[i * 3 + c];
-  return s + half_src;
-}
-
 template <typename S>
 __device__ __forceinline__ void forcing_at(const StepArgs<S>& a, uint32_t cell, typename Enc<S>::R (&F)[3],
                                            typename Enc<S>::R (&Sb)[3]) {
@@ -207,8 +197,8 @@ template <typename S, bool FAA, bool MAA, int PAR, bool SAVE>
 __global__ __launch_bounds__(kLocalThreads) void step_local(StepArgs<S> a) {
   using R = typename Enc<S>::R;
   unsigned bx, by, bz;
-  logical_block((a.nx + kLocalThreads - 1) / kLocalThreads, a.ny, a.nz, bx, by, bz);
-  const int x = bx * kLocalThreads + threadIdx.x;
+  logical_block((a.nx + blockDim.x - 1) / blockDim.x, a.ny, a.nz, bx, by, bz);
+  const int x = bx * blockDim.x + threadIdx.x;
   const int y = by;
   const int z = bz;
   if (x >= a.nx) return;
@@ -419,8 +409,9 @@ static hipError_t launch_typed(const flame_ctx* c, const SetPtrs& s, size_t stri
       hipLaunchKernelGGL((step_zmarch<S, true, 1, SAVE>), grid, block, 0, c->stream, a);
   } else {
     a.zchunk = 1;
-    const dim3 block(kLocalThreads, 1, 1);
-    const dim3 grid(((c->p.nx + kLocalThreads - 1) / kLocalThreads) * c->p.ny * c->p.nz);
+    const unsigned tx = row_threads(c->p.nx);
+    const dim3 block(tx, 1, 1);
+    const dim3 grid(((c->p.nx + tx - 1) / tx) * c->p.ny * c->p.nz);
     if (!s.fluid_aa)
       hipLaunchKernelGGL((step_local<S, false, false, 0, SAVE>), grid, block, 0, c->stream, a);
     else if (par == 0)

@@ -1,4 +1,6 @@
-"""GPU adjoint (reverse mode through the C ABI) of a rollout of the step:
+"""GPU adjoint (reverse mode through the C ABI) of a rollout of the step, for each way of
+recomputing a checkpoint segment (moment route: trace lattices and saved states; stencil route:
+saved states):
   * gradient of a magnetic-spectrum misfit w.r.t. the initial u and b against central finite
     differences of the same GPU forward (FP64 storage);
   * against torch autograd through the CPU oracle's rollout (definition route), FP64;
@@ -24,9 +26,14 @@ def _fields(n, seed=0):
     return u, b, fu, fb
 
 
-def _cfg(n, jmode, storage, steps, ckpt, fu, fb):
+ROUTES = ["moment-trace", "moment-state", "stencil-state"]
+
+
+def _cfg(n, route, storage, steps, ckpt, fu, fb):
     from paper_2212_11024_amd.adjoint import RolloutConfig
-    return RolloutConfig(n, n, n, 0.02, 0.03, 2.0, (0.01, -0.02, 0.04), storage, jmode, "aa", steps, ckpt, fu, fb)
+    jmode, recompute = route.split("-")
+    return RolloutConfig(n, n, n, 0.02, 0.03, 2.0, (0.01, -0.02, 0.04), storage, jmode, "aa", steps, ckpt, fu, fb,
+                         recompute)
 
 
 def _loss(B, target, nshells):
@@ -51,13 +58,13 @@ def _gpu_loss(u, b, cfg, target, nshells):
         return float(_loss(B, target.cuda(), nshells))
 
 
-@pytest.mark.parametrize("jmode", ["moment", "stencil"])
-def test_adjoint_matches_central_differences(jmode):
+@pytest.mark.parametrize("route", ROUTES)
+def test_adjoint_matches_central_differences(route):
     """16 seeded solenoidal directions (shells 1..5, unit rms), step 1e-4 of the field rms."""
     n, steps, ckpt, nshells = 12, 24, 8, 6
-    print(f"[adjoint] FD {jmode}", flush=True)
+    print(f"[adjoint] FD {route}", flush=True)
     u, b, fu, fb = _fields(n)
-    cfg = _cfg(n, jmode, "f64", steps, ckpt, fu, fb)
+    cfg = _cfg(n, route, "f64", steps, ckpt, fu, fb)
     target = torch.linspace(1e-5, 2e-6, nshells, dtype=torch.float64)
     loss, gu, gb = _gpu_grad(u, b, cfg, target, nshells)
     for j in range(16):
@@ -68,7 +75,7 @@ def test_adjoint_matches_central_differences(jmode):
         lm = _gpu_loss(u - eps * du, b - eps * db, cfg, target, nshells)
         fd = (lp - lm) / (2 * eps)
         ad = float((gu * du).sum() + (gb * db).sum())
-        print(f"[adjoint] {jmode} direction {j}: adjoint {ad:.10e} fd {fd:.10e} rel {abs(ad - fd) / abs(fd):.2e}",
+        print(f"[adjoint] {route} direction {j}: adjoint {ad:.10e} fd {fd:.10e} rel {abs(ad - fd) / abs(fd):.2e}",
               flush=True)
         assert abs(ad - fd) <= 1e-6 * abs(fd)
 
@@ -106,32 +113,32 @@ def _oracle_grad(u, b, cfg, target, nshells):
     return torch.autograd.grad(loss, (u0, b0))
 
 
-@pytest.mark.parametrize("jmode", ["moment", "stencil"])
-def test_adjoint_matches_oracle_autograd(jmode):
+@pytest.mark.parametrize("route", ROUTES)
+def test_adjoint_matches_oracle_autograd(route):
     """16^3, 50 steps in checkpoint segments of 10, forced, both J routes."""
     n, steps, ckpt, nshells = 16, 50, 10, 8
-    print(f"[adjoint] oracle {jmode}", flush=True)
+    print(f"[adjoint] oracle {route}", flush=True)
     u, b, fu, fb = _fields(n, seed=3)
-    cfg = _cfg(n, jmode, "f64", steps, ckpt, fu, fb)
+    cfg = _cfg(n, route, "f64", steps, ckpt, fu, fb)
     target = torch.linspace(1e-5, 2e-6, nshells, dtype=torch.float64)
     _, gu, gb = _gpu_grad(u, b, cfg, target, nshells)
     ou, ob = _oracle_grad(u, b, cfg, target, nshells)
     rel = float(torch.sqrt(((gu - ou) ** 2).sum() + ((gb - ob) ** 2).sum()) /
                 torch.sqrt((ou ** 2).sum() + (ob ** 2).sum()))
-    print(f"[adjoint] {jmode} GPU vs oracle autograd: relative {rel:.2e}", flush=True)
+    print(f"[adjoint] {route} GPU vs oracle autograd: relative {rel:.2e}", flush=True)
     assert rel < 1e-10
 
 
-@pytest.mark.parametrize("jmode", ["moment", "stencil"])
-def test_fp32_adjoint_tracks_fp64(jmode):
+@pytest.mark.parametrize("route", ROUTES)
+def test_fp32_adjoint_tracks_fp64(route):
     n, steps, ckpt, nshells = 12, 30, 10, 6
     u, b, fu, fb = _fields(n, seed=5)
     target = torch.linspace(1e-5, 2e-6, nshells, dtype=torch.float64)
-    _, gu64, gb64 = _gpu_grad(u, b, _cfg(n, jmode, "f64", steps, ckpt, fu, fb), target, nshells)
-    _, gu32, gb32 = _gpu_grad(u, b, _cfg(n, jmode, "f32", steps, ckpt, fu, fb), target, nshells)
+    _, gu64, gb64 = _gpu_grad(u, b, _cfg(n, route, "f64", steps, ckpt, fu, fb), target, nshells)
+    _, gu32, gb32 = _gpu_grad(u, b, _cfg(n, route, "f32", steps, ckpt, fu, fb), target, nshells)
     a = torch.cat([gu64.reshape(-1), gb64.reshape(-1)])
     c = torch.cat([gu32.reshape(-1), gb32.reshape(-1)])
     cos = float((a * c).sum() / (a.norm() * c.norm()))
     rel = float((a - c).norm() / a.norm())
-    print(f"[adjoint] {jmode} FP32 vs FP64: cosine {cos:.6f}, relative {rel:.2e}", flush=True)
+    print(f"[adjoint] {route} FP32 vs FP64: cosine {cos:.6f}, relative {rel:.2e}", flush=True)
     assert cos > 0.999 and rel < 1e-3
