@@ -28,6 +28,8 @@ CASES = {
     "hall_strong": Case(9, 8, 7, jmode="moment", d_i=8.0, seed=3),
     "forced": Case(12, 8, 8, jmode="stencil", forced=True, seed=5),
     "wide_x": Case(70, 5, 3, jmode="stencil", seed=7),
+    # rows longer than one workgroup (256 nodes): the second block of each row is ragged
+    "long_x": Case(257, 3, 3, jmode="moment", forced=True, seed=9),
 }
 
 
