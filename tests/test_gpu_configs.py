@@ -77,3 +77,68 @@ def test_decaying_turbulence_256_fp32_tracks_fp64():
     assert weighted < 3e-4
     assert float(per_shell[1:5].max()) < 3e-4
     assert float(per_shell[5:9].max()) < 3e-3
+
+
+def test_adjoint_configuration_128():
+    """The differentiation configuration: 128^3, fields as in the decaying run, nu = eta = 0.002,
+    d_i = 4, 1000 steps with checkpoints every 50; loss = sum over shells 1..64 of the squared
+    misfit of the final magnetic energy spectrum to the spectrum of the same start run with
+    d_i = 0. The FP64 gradient with respect to (u0, b0) against central finite differences
+    along seeded solenoidal directions (shells 1..8, unit rms), bar 1e-4. The loss is a squared
+    misfit of small spectral differences, so its curvature is large against its gradient: a step
+    of 1e-4 (0.5% of the field rms) leaves an O(eps^2) truncation of order 1e-2, which the run
+    prints together with the steps 1e-5 and 1e-6 to show the eps^2 convergence; the bar applies
+    at 1e-6, where FP64 rounding of the loss difference is still ~1e-10 of it. The FP32 gradient
+    against the FP64 one (direction and size)."""
+    from paper_2212_11024_amd.adjoint import RolloutConfig, rollout, shell_spectrum
+    from paper_2212_11024_amd.solver import Solver
+    n, steps, ckpt, nsh = 128, 1000, 50, 65
+    shape = (n, n, n)
+    u, gu = synthetic.evaluate(synthetic.shell_field(0, 1, 4, 0.02), shape, "cuda")
+    b, gb = synthetic.evaluate(synthetic.shell_field(1, 1, 4, 0.02), shape, "cuda")
+    print("[config4] target run (d_i = 0)", flush=True)
+    t = Solver(n, n, n, 0.002, 0.002, 0.0, (0.0, 0.0, 0.0), "f64", "moment", "aa", u, b, gu, gb)
+    t.step(steps)
+    target = t.spectrum("B", nsh).cuda()
+    t.close()
+    del gu, gb
+
+    def cfg(storage):
+        return RolloutConfig(n, n, n, 0.002, 0.002, 4.0, (0.0, 0.0, 0.0), storage, "moment", "aa", steps, ckpt)
+
+    def loss_of(B):
+        e = shell_spectrum(B, nsh)
+        return ((e[1:] - target[1:]) ** 2).sum()
+
+    grads = {}
+    for storage in ("f64", "f32"):
+        u0 = u.clone().requires_grad_(True)
+        b0 = b.clone().requires_grad_(True)
+        _, B = rollout(u0, b0, cfg(storage))
+        L = loss_of(B)
+        grads[storage] = torch.autograd.grad(L, (u0, b0))
+        print(f"[config4] {storage}: loss {float(L):.6e}", flush=True)
+
+    def loss_at(du, db, eps):
+        with torch.no_grad():
+            _, B = rollout(u + eps * du, b + eps * db, cfg("f64"))
+            return float(loss_of(B))
+
+    gu64, gb64 = grads["f64"]
+    for j in range(2):
+        du, _ = synthetic.evaluate(synthetic.shell_field(100 + j, 1, 8, 1.0), shape, "cuda", gradient=False)
+        db, _ = synthetic.evaluate(synthetic.shell_field(200 + j, 1, 8, 1.0), shape, "cuda", gradient=False)
+        ad = float((gu64 * du).sum() + (gb64 * db).sum())
+        rels = []
+        for eps in (1e-4, 1e-5, 1e-6):
+            fd = (loss_at(du, db, eps) - loss_at(du, db, -eps)) / (2 * eps)
+            rels.append(abs(ad - fd) / abs(fd))
+            print(f"[config4] direction {j}, step {eps:g}: adjoint {ad:.10e} fd {fd:.10e} rel {rels[-1]:.2e}",
+                  flush=True)
+        assert rels[-1] < 1e-4 and rels[-1] < rels[0]
+    a = torch.cat([g.reshape(-1) for g in grads["f64"]])
+    c = torch.cat([g.reshape(-1) for g in grads["f32"]])
+    cos = float((a * c).sum() / (a.norm() * c.norm()))
+    rel = float((a - c).norm() / a.norm())
+    print(f"[config4] FP32 vs FP64 gradient: cosine {cos:.6f}, relative {rel:.2e}", flush=True)
+    assert cos > 0.999 and rel < 1e-3
