@@ -476,10 +476,13 @@ std::string validate(const flame_params* p) {
   const double cells = static_cast<double>(p->nx) * p->ny * p->nz;
   if (cells >= 1099511627776.0) return "grid too large (nx*ny*nz must be < 2^40)";
   if (p->nz > 65535) return "nz must be <= 65535";
-  // kernels address each population and forcing array with 32-bit byte offsets
+  // kernels address each population and forcing array with 32-bit byte offsets: every array,
+  // with its stride padding, must span at most 4 GiB (largest offset 4 GiB minus one value)
   const double vb = p->storage == FLAME_F64 ? 8.0 : p->storage == FLAME_F32 ? 4.0 : 2.0;
   const double fb = p->storage == FLAME_F64 ? 8.0 : 4.0;
-  if ((cells + 256.0 + FLAME_STRIDE_PAD_BYTES) * vb > 4294967296.0 || cells * fb > 4294967296.0)
+  const bool forced = p->force_u || p->force_b;
+  if (cells >= 4294967296.0 || static_cast<double>(population_stride(*p)) * vb > 4294967296.0 ||
+      (forced && cells * fb > 4294967296.0))
     return "grid too large: each population / forcing array must fit in 4 GiB";
   if (!(p->nu > 0) || !isfinite(p->nu)) return "nu must be finite and > 0";
   if (!(p->eta > 0) || !isfinite(p->eta)) return "eta must be finite and > 0";

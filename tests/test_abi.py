@@ -59,6 +59,21 @@ def test_storage_bytes(lib):
     assert L.flame_storage_bytes(_params(shape=(512, 512, 512))) == 48 * 4 * 512 ** 3
 
 
+def test_array_size_limit(lib):
+    """Each population array is addressed with 32-bit byte offsets: 1024^3 FP32 arrays (exactly
+    4 GiB) are accepted, one more plane is not; FP16 and FP64 limits scale with the value size."""
+    g = 1024
+    assert L.flame_storage_bytes(_params(shape=(g, g, g))) == 48 * 4 * g ** 3
+    assert L.flame_storage_bytes(_params(shape=(g, g, g + 1))) == 0
+    assert L.flame_storage_bytes(_params(shape=(g, g, 2 * g), storage=L.FLAME_F16)) == 48 * 2 * 2 * g ** 3
+    assert L.flame_storage_bytes(_params(shape=(g, g, 2 * g + 1), storage=L.FLAME_F16)) == 0
+    assert L.flame_storage_bytes(_params(shape=(g, g, g // 2), storage=L.FLAME_F64)) == 48 * 8 * g ** 3 // 2
+    assert L.flame_storage_bytes(_params(shape=(g, g, g // 2 + 1), storage=L.FLAME_F64)) == 0
+    forced = _params(shape=(g, g, 2 * g), storage=L.FLAME_F16)
+    forced.force_u = 256                  # forcing arrays are FP32 [3][n]: 8 GiB each, too large
+    assert L.flame_storage_bytes(forced) == 0
+
+
 @pytest.mark.parametrize("kw,msg", [
     ({"nu": 0.0}, "nu"), ({"eta": -1.0}, "eta"), ({"d_i": -2.0}, "d_i"), ({"shape": (0, 4, 4)}, "grid"),
     ({"shape": (2, 8, 8), "jmode": L.FLAME_J_STENCIL}, "stencil"), ({"storage": 7}, "storage"),
