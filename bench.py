@@ -239,27 +239,45 @@ def copy_probe(gib=4, reps=5):
 
 
 def cpu_baseline(seconds=15.0):
-    """The FP64 oracle (closed-form route, as it stands) on a 32^3 sample of the workload's
-    physics (moment-route J, like the headline), on the host cores; MLUPS = nodes x steps / time."""
+    """The FP64 oracle, as it stands, on a 32^3 sample of the workload's physics (moment-route J,
+    forced, like the headline) on the host cores: MLUPS = nodes x steps / time. The value is the
+    closed-form collision route with all threads (60% of the time budget); the T-matrix route
+    (the definition, 25%) and a single-thread run of the closed form (15%) are reported beside
+    it, with the host's CPU model."""
     import torch
     from oracle import scheme
-    torch.set_num_threads(int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     n = 32
     u, gu, b, gb, fu, fb = workload_fields(n, "cpu")
-    p = scheme.Params(n, n, n, PHYS["nu"], PHYS["eta"], PHYS["d_i"], PHYS["b0"], "moment", "closed", fu, fb)
-    st = scheme.init_state(p, u, b, gu, gb)
-    st = scheme.step(st, p, 1)                  # warm-up
-    steps, t0 = 0, time.perf_counter()
-    while True:
-        st = scheme.step(st, p, 1)
-        steps += 1
-        el = time.perf_counter() - t0
-        if el >= seconds:
-            break
-    return {"value": n ** 3 * steps / el / 1e6, "unit": "MLUPS", "cores": torch.get_num_threads(),
-            "kind": "oracle",
+
+    def rate(route, budget, nthreads):
+        torch.set_num_threads(nthreads)
+        p = scheme.Params(n, n, n, PHYS["nu"], PHYS["eta"], PHYS["d_i"], PHYS["b0"], "moment", route, fu, fb)
+        st = scheme.init_state(p, u, b, gu, gb)
+        st = scheme.step(st, p, 1)                  # warm-up
+        steps, t0 = 0, time.perf_counter()
+        while True:
+            st = scheme.step(st, p, 1)
+            steps += 1
+            el = time.perf_counter() - t0
+            if el >= budget:
+                return n ** 3 * steps / el / 1e6, steps, el
+
+    closed, steps, el = rate("closed", 0.60 * seconds, threads)
+    tmat = rate("T", 0.25 * seconds, threads)
+    single = rate("closed", 0.15 * seconds, 1)
+    torch.set_num_threads(threads)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
+    return {"value": closed, "unit": "MLUPS", "cores": threads, "kind": "oracle",
             "sample": f"32^3 nodes, {steps} steps of the workload physics (moment J, forced), "
-                      f"FP64 closed-form route, {el:.1f} s"}
+                      f"FP64 closed-form route, {el:.1f} s",
+            "t_matrix_route_MLUPS": round(tmat[0], 4), "single_thread_MLUPS": round(single[0], 4),
+            "host_cpu": model, "host_logical_cpus": os.cpu_count()}
 
 
 def main(argv=None):

@@ -63,7 +63,8 @@ typedef int32_t flame_status;
 #define FLAME_J_STENCIL 1  /* central-difference curl of B over the six face neighbours */
 
 /* Population layout in the caller's storage buffer.
- * AB: two lattices for each set, push streaming.
+ * AB: two lattices for each set, pull streaming (a step reads population i of node x at
+ *     x - c_i in one copy and writes it at x in the other).
  * AA: one lattice updated in place (even/odd step addressing); with FLAME_J_STENCIL the
  *     magnetic set keeps two lattices so that neighbour fields are read-only in a step. */
 #define FLAME_LAYOUT_AB 0
@@ -80,7 +81,8 @@ typedef int32_t flame_status;
 
 typedef struct {
   int32_t nx, ny, nz;   /* grid; each >= 1 (>= 3 with FLAME_J_STENCIL), nz <= 65535; one population
-                           array (nx*ny*nz values) and one forcing array must each fit in 4 GiB */
+                           array (nx*ny*nz values, padded to 256 bytes) and, when forcing is
+                           given, one forcing array must each span at most 4 GiB */
   double nu;            /* lattice kinematic viscosity, > 0 */
   double eta;           /* lattice resistivity, > 0 */
   double d_i;           /* Hall coefficient alpha_H in cells (ion inertial length, rho0 = 1), >= 0 */
@@ -124,7 +126,8 @@ flame_status flame_init(const flame_params* p, const double* u, const double* b,
                         const double* grad_u, const double* grad_b, void* storage,
                         size_t storage_bytes, void* hip_stream, flame_ctx** out);
 
-/* Advance nsteps >= 0 time steps (one fused kernel launch per step), asynchronously. */
+/* Advance nsteps >= 0 time steps, asynchronously: per step one fused kernel launch that
+ * collides (Sec. 3.1.2 fluid, Sec. 3.2 magnetic) and streams (eq. stream) every node. */
 flame_status flame_step(flame_ctx* c, int64_t nsteps);
 
 /* Node fields of the current state into nullable device double buffers:
@@ -182,7 +185,7 @@ flame_status flame_adjoint_step(flame_ctx* c, const void* state, const void* lam
  * at x - c_q. flame_trace_bytes(c) bytes each (0 if c is NULL). flame_trace_export writes the
  * current state (exact: stored values are moved, not recoded); flame_trace_step advances a
  * lattice src by one step into dst (dst must not alias src) without touching the context, and
- * reproduces the context's own steps bitwise. Other routes and layouts get FLAME_E_INVAL. */
+ * reproduces the context's own steps bitwise. Other routes and layouts get FLAME_E_UNSUPPORTED. */
 size_t flame_trace_bytes(const flame_ctx* c);
 flame_status flame_trace_export(flame_ctx* c, void* lat);
 flame_status flame_trace_step(flame_ctx* c, const void* src, void* dst);
@@ -190,7 +193,8 @@ flame_status flame_trace_step(flame_ctx* c, const void* src, void* dst);
 /* Moment route: lam = (d step / d x)^T lam_next for the step whose pre-collision state is the
  * trace lattice src pulled (the step flame_trace_step takes from src), with J recomputed from
  * that state; the same reverse pass as flame_adjoint_step without a saved state. lam, lam_next
- * as for flame_adjoint_step; lam must not alias lam_next. */
+ * as for flame_adjoint_step; lam must not alias lam_next. The stencil route gets
+ * FLAME_E_UNSUPPORTED. */
 flame_status flame_adjoint_trace_step(flame_ctx* c, const void* src, const void* lam_next, void* lam);
 
 /* lam = adjoint of the current state for a loss of its node fields: dl_du, dl_db (device

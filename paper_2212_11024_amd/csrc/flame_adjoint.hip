@@ -337,7 +337,7 @@ flame_status flame_trace_step(flame_ctx* c, const void* src, void* dst) {
   if (!c) return FLAME_E_INVAL;
   if (c->p.jmode != FLAME_J_MOMENT) {
     c->err = "trace step is available on the moment route only";
-    return FLAME_E_INVAL;
+    return FLAME_E_UNSUPPORTED;
   }
   if (!src || !dst || src == dst) {
     c->err = "trace step needs distinct src and dst";
@@ -378,7 +378,7 @@ flame_status flame_adjoint_trace_step(flame_ctx* c, const void* src, const void*
   if (!c) return FLAME_E_INVAL;
   if (c->p.jmode != FLAME_J_MOMENT) {
     c->err = "the trace adjoint is available on the moment route only";
-    return FLAME_E_INVAL;
+    return FLAME_E_UNSUPPORTED;
   }
   if (!src || !lam_next || !lam || lam == lam_next) {
     c->err = "trace adjoint needs src, lam_next and a distinct lam";

@@ -892,7 +892,7 @@ flame_status flame_trace_export(flame_ctx* c, void* lat) {
   if (!c) return FLAME_E_INVAL;
   if (!lat) return fail(c, FLAME_E_INVAL, "lat is NULL");
   if (c->p.layout != FLAME_LAYOUT_AA || c->p.jmode != FLAME_J_MOMENT)
-    return fail(c, FLAME_E_INVAL, "trace export is available on the moment route with the AA layout only");
+    return fail(c, FLAME_E_UNSUPPORTED, "trace export is available on the moment route with the AA layout only");
   hipError_t e = by_storage(c, [&](auto tag) {
     using S = decltype(tag);
     hipLaunchKernelGGL(export_kernel<S>, dim3(blocks_for(c->n, 256)), dim3(256), 0, c->stream, make_view<S>(c),

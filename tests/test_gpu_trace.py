@@ -2,7 +2,8 @@
   * exporting the state and stepping the exported lattice with flame_trace_step reproduces the
     context's own steps bitwise (every storage, ragged forced grid) and leaves the context
     untouched;
-  * the routes and layouts the trace entry points do not serve are refused, not launched.
+  * the routes and layouts the trace entry points do not serve are refused with
+    FLAME_E_UNSUPPORTED, bad arguments with FLAME_E_INVAL, and nothing is launched.
 
 The stencil route and the two-lattice (AB) layout are switched off in the library: the first GPU
 run of each (export from a two-copy magnetic set, the pull z-marching step) ended in a memory
@@ -69,9 +70,14 @@ def test_trace_argument_errors():
     for jmode, layout in (("stencil", "aa"), ("moment", "ab")):
         s = gpu_solver(Case(8, 6, 5, jmode=jmode), "f32", layout)
         lat = torch.empty((2, L.flame_trace_bytes(s.ctx)), dtype=torch.uint8, device=s.device)
-        with pytest.raises(L.FlameError):
+        with pytest.raises(L.FlameError) as e:
             L.flame_trace_export(s.ctx, lat[0].data_ptr())        # switched off
+        assert e.value.code == L.FLAME_E_UNSUPPORTED
         if jmode == "stencil":
-            with pytest.raises(L.FlameError):
-                L.flame_trace_step(s.ctx, lat[0].data_ptr(), lat[1].data_ptr())
+            for call in (lambda: L.flame_trace_step(s.ctx, lat[0].data_ptr(), lat[1].data_ptr()),
+                         lambda: L.flame_adjoint_trace_step(s.ctx, lat[0].data_ptr(), lat[1].data_ptr(),
+                                                            lat[0].data_ptr())):
+                with pytest.raises(L.FlameError) as e:
+                    call()
+                assert e.value.code == L.FLAME_E_UNSUPPORTED
         s.close()
