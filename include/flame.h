@@ -117,8 +117,10 @@ flame_status flame_rest_populations(const flame_params* p, double* f_rest, doubl
  * -(1/omega_B) W_i xi_ia d_a B_b). With forcing, -F/2 and -S/2 shifts make the node moments
  * return exactly u and B = b0 + b.
  *   u, b: device double [3][nz][ny][nx] (velocity; field fluctuation, B = b0 + b).
- *   grad_u, grad_b: device double [3][3][nz][ny][nx] or NULL (then no non-equilibrium part
- *     and J = 0 in the initial Hall equilibrium).
+ *   grad_u, grad_b: device double [3][3][nz][ny][nx] or NULL. A NULL gradient is replaced,
+ *     when init_noneq is set, by the central difference of u (or b) on the grid,
+ *     (v(x + e_a) - v(x - e_a)) / 2; without init_noneq a NULL grad_b gives J = 0 in the initial
+ *     Hall equilibrium and no non-equilibrium part is added.
  *   storage: device, at least flame_storage_bytes(p) bytes, 256-byte aligned.
  *   hip_stream: hipStream_t (NULL = default stream).
  * Returns FLAME_OK or FLAME_W_CFL with *out set; on error *out is NULL. */
@@ -204,7 +206,9 @@ flame_status flame_adjoint_fields(flame_ctx* c, const double* dl_du, const doubl
 
 /* Adjoint of the initial state of flame_init: from lam0 (d loss / d initial deviations) and the
  * same u, b, grad_u, grad_b that flame_init received, write g_u, g_b (device double [3][n]) and,
- * when non-NULL, g_grad_u, g_grad_b ([3][3][n]). */
+ * when non-NULL, g_grad_u, g_grad_b ([3][3][n]). With init_noneq both gradients must be given
+ * (FLAME_E_UNSUPPORTED otherwise: the transpose of the internal central differences is not
+ * built). */
 flame_status flame_adjoint_init(flame_ctx* c, const void* lam0, const double* u, const double* b,
                                 const double* grad_u, const double* grad_b, double* g_u, double* g_b,
                                 double* g_grad_u, double* g_grad_b);

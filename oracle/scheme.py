@@ -133,6 +133,15 @@ def step(st: State, p: Params, nsteps: int = 1) -> State:
     return st
 
 
+def central_gradient(v):
+    """grad[a, b] = (v_b(x + e_a) - v_b(x - e_a)) / 2 on the periodic grid, v of shape
+    (3, nz, ny, nx): the second-order central difference that stands in for exact gradients
+    at initialisation when none are given (the same stencil as the curl route of J)."""
+    axis = {0: 3, 1: 2, 2: 1}          # tensor dimension of x, y, z
+    return torch.stack([0.5 * (torch.roll(v, -1, dims=axis[a]) - torch.roll(v, 1, dims=axis[a]))
+                        for a in range(3)])
+
+
 def curl_from_gradient(grad):
     """(curl B)_g from grad[a, b] = d_a B_b."""
     return torch.stack([grad[1, 2] - grad[2, 1], grad[2, 0] - grad[0, 2], grad[0, 1] - grad[1, 0]])

@@ -97,9 +97,12 @@ class FlameRollout(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, u0, b0, gu0, gb0, cfg: RolloutConfig):
+        if (gu0 is None) != (gb0 is None):
+            raise ValueError("pass both initial gradients or neither")
+        # without gradients the run starts at equilibrium (no non-equilibrium parts, J = 0)
         s = Solver(cfg.nx, cfg.ny, cfg.nz, cfg.nu, cfg.eta, cfg.d_i, cfg.b0, cfg.storage, cfg.jmode, cfg.layout,
                    u0.detach(), b0.detach(), None if gu0 is None else gu0.detach(),
-                   None if gb0 is None else gb0.detach(), cfg.force_u, cfg.force_b)
+                   None if gb0 is None else gb0.detach(), cfg.force_u, cfg.force_b, init_noneq=gu0 is not None)
         trace = cfg.uses_trace()
         ckpts = []
         done = 0

@@ -405,6 +405,11 @@ flame_status flame_adjoint_init(flame_ctx* c, const void* lam0, const double* u,
     c->err = "adjoint init needs lam0, u, b, g_u and g_b";
     return FLAME_E_INVAL;
   }
+  if (c->p.init_noneq && (!grad_u || !grad_b)) {
+    c->err = "adjoint init needs the gradients that flame_init received (the transpose of the "
+             "central differences taken in their absence is not built)";
+    return FLAME_E_UNSUPPORTED;
+  }
   hipError_t e = c->p.storage == FLAME_F64
                      ? init_vjp_typed<double>(c, lam0, u, b, grad_u, grad_b, g_u, g_b, g_grad_u, g_grad_b)
                      : init_vjp_typed<float>(c, lam0, u, b, grad_u, grad_b, g_u, g_b, g_grad_u, g_grad_b);

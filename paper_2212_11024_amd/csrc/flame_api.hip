@@ -200,22 +200,44 @@ __global__ __launch_bounds__(256) void init_kernel(InitArgs<S> a) {
     if (a.force_u) F[c] = static_cast<double>(a.force_u[c * n + cell]);
     if (a.force_b) Sb[c] = static_cast<double>(a.force_b[c * n + cell]);
   }
+  // gradients: given, or (with the non-equilibrium initialisation) central differences on the grid
+  auto central = [&](const double* v, double (&g)[3][3]) {
+    auto at = [&](int x, int y, int z) { return (static_cast<size_t>(z) * a.ny + y) * a.nx + x; };
+    const size_t xm = at(wrap(px - 1, a.nx), py, pz), xp = at(wrap(px + 1, a.nx), py, pz);
+    const size_t ym = at(px, wrap(py - 1, a.ny), pz), yp = at(px, wrap(py + 1, a.ny), pz);
+    const size_t zm = at(px, py, wrap(pz - 1, a.nz)), zp = at(px, py, wrap(pz + 1, a.nz));
+    for (int c = 0; c < 3; ++c) {
+      const double* vc = v + c * n;
+      g[0][c] = 0.5 * (vc[xp] - vc[xm]);
+      g[1][c] = 0.5 * (vc[yp] - vc[ym]);
+      g[2][c] = 0.5 * (vc[zp] - vc[zm]);
+    }
+  };
   double gu[3][3] = {}, gb[3][3] = {};
-  if (a.gu)
+  bool have_gu = a.gu != nullptr, have_gb = a.gb != nullptr;
+  if (a.gu) {
     for (int p = 0; p < 3; ++p)
       for (int q = 0; q < 3; ++q) gu[p][q] = a.gu[(p * 3 + q) * n + cell];
-  if (a.gb)
+  } else if (a.noneq) {
+    central(a.u, gu);
+    have_gu = true;
+  }
+  if (a.gb) {
     for (int p = 0; p < 3; ++p)
       for (int q = 0; q < 3; ++q) gb[p][q] = a.gb[(p * 3 + q) * n + cell];
+  } else if (a.noneq) {
+    central(a.b, gb);
+    have_gb = true;
+  }
   PhysConst<double> k;
   k.omega = a.omega;
   k.omega_b = a.omega_b;
   k.alpha = a.alpha;
   for (int c = 0; c < 3; ++c) k.b0[c] = a.b0[c];
   InitFlags fl;
-  fl.fluid_noneq = a.noneq && a.gu;
-  fl.mag_noneq = a.noneq && a.gb;
-  fl.has_H = a.gb != nullptr;
+  fl.fluid_noneq = a.noneq && have_gu;
+  fl.mag_noneq = a.noneq && have_gb;
+  fl.has_H = have_gb;
   double f[kQ], g[kM];
   init_node(U, b, gu, gb, F, Sb, k, fl, f, g);
   for (int i = 0; i < kQ; ++i)

@@ -23,7 +23,8 @@ class Solver:
     """One periodic nx x ny x nz Hall-MHD LB run on the current HIP device.
 
     u, b: (3, nz, ny, nx) float64 (velocity; field fluctuation, B = b0 + b).
-    grad_u, grad_b: (3, 3, nz, ny, nx) float64, grad[a, b] = d_a f_b, or None.
+    grad_u, grad_b: (3, 3, nz, ny, nx) float64, grad[a, b] = d_a f_b, or None; with
+    init_noneq a None gradient is taken by central differences on the grid.
     force_u, force_b: (3, nz, ny, nx) static forcing (any float dtype; converted to the
     storage's arithmetic type: float64 for "f64", float32 otherwise), or None.
     """

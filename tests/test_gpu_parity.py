@@ -237,3 +237,20 @@ def test_fp16_storage_tracks_fp32():
     b.step(50)
     print("deviation error after 50 steps: f16", err, "f32", extended_error(b, ref), flush=True)
     assert err < 5e-3
+
+
+@pytest.mark.parametrize("jmode", ["moment", "stencil"])
+def test_initial_state_from_central_differences(jmode):
+    # no gradients passed, non-equilibrium initialisation on: the library takes central
+    # differences of u and b on the grid, which the oracle receives explicitly
+    from paper_2212_11024_amd.solver import Solver
+    case = Case(11, 9, 7, jmode=jmode, forced=True, seed=21)
+    _print_case("central-difference init", jmode=jmode)
+    u, gu, b, gb, fu, fb = inputs(case)
+    s = Solver(case.nx, case.ny, case.nz, case.nu, case.eta, case.d_i, case.b0, "f64", jmode, "aa",
+               u, b, None, None, fu, fb, init_noneq=True)
+    p = scheme.Params(case.nx, case.ny, case.nz, case.nu, case.eta, case.d_i, case.b0, jmode, "closed", fu, fb)
+    st = scheme.init_state(p, u, b, scheme.central_gradient(u), scheme.central_gradient(b))
+    assert deviation_error(s, p, st) < 1e-14
+    s.step(5)
+    assert deviation_error(s, p, scheme.step(st, p, 5)) < 1e-13

@@ -206,3 +206,26 @@ def test_divergence_estimate_of_trace():
     Lam = torch.randn(3, 3, 5, dtype=torch.float64)
     d = cur.divergence_moment(Lam, 1.6)
     assert torch.allclose(d, -(1.6 / C2) * (Lam[0, 0] + Lam[1, 1] + Lam[2, 2]))
+
+
+def test_central_gradient_single_modes():
+    # central difference of a Fourier mode along each axis = (sin k / k) x exact derivative,
+    # with the derivative direction first: grad[a, b] = d_a v_b
+    from oracle import scheme
+    n = 12
+    x = torch.arange(n, dtype=torch.float64)
+    v = torch.zeros(3, n, n, n, dtype=torch.float64)
+    ks = {}
+    for b, (axis, m) in enumerate(((0, 1), (1, 2), (2, 5))):     # v_b varies along axis b only
+        k = 2 * math.pi * m / n
+        shape = [1, 1, 1]
+        shape[2 - axis] = n                                          # (z, y, x) tensor dims
+        v[b] = torch.sin(k * x.view(shape)).expand(n, n, n)
+        ks[b] = (axis, k, shape)
+    g = scheme.central_gradient(v)
+    for b, (axis, k, shape) in ks.items():
+        exact = k * torch.cos(k * x.view(shape)).expand(n, n, n)
+        assert (g[axis, b] - math.sin(k) / k * exact).abs().max() < 1e-14
+        for a in range(3):
+            if a != axis:
+                assert g[a, b].abs().max() == 0.0
