@@ -254,3 +254,62 @@ def test_initial_state_from_central_differences(jmode):
     assert deviation_error(s, p, st) < 1e-14
     s.step(5)
     assert deviation_error(s, p, scheme.step(st, p, 5)) < 1e-13
+
+
+def _gpu_from(case, u, gu, b, gb, storage="f64"):
+    from paper_2212_11024_amd.solver import Solver
+    return Solver(case.nx, case.ny, case.nz, case.nu, case.eta, case.d_i, case.b0, storage, case.jmode, "aa",
+                  u, b, gu, gb)
+
+
+@pytest.mark.parametrize("jmode", ["moment", "stencil"])
+def test_ideal_mhd_limit(jmode):
+    # d_i = 0: no Hall term (the moment-route solve reduces to the ideal one, the stencil J is unused)
+    case = Case(9, 8, 7, jmode=jmode, d_i=0.0, seed=31)
+    _print_case("ideal MHD", jmode=jmode)
+    s = gpu_solver(case, "f64", "aa")
+    s.step(21)
+    assert extended_error(s, extended_run(case, 21)) < TOL["f64"]
+
+
+def test_field_free_flow_stays_field_free():
+    # b = 0 and b0 = 0: pure hydrodynamics; the magnetic populations stay exactly at rest
+    case = Case(10, 9, 8, jmode="moment", b0=(0.0, 0.0, 0.0), seed=33)
+    _print_case("field-free")
+    u, gu, b, gb, _, _ = inputs(case)
+    b, gb = torch.zeros_like(b), torch.zeros_like(gb)
+    s = _gpu_from(case, u, gu, b, gb)
+    p = scheme.Params(case.nx, case.ny, case.nz, case.nu, case.eta, case.d_i, case.b0, "moment", "closed")
+    st = scheme.step(scheme.init_state(p, u, b, gu, gb), p, 21)
+    s.step(21)
+    assert deviation_error(s, p, st) < 1e-12
+    _, g = s.get_populations(deviations=True)
+    assert int(torch.count_nonzero(g)) == 0
+
+
+def test_one_node_thick_grid():
+    # nx = 1 (a periodic 2-D flow in y, z): every x-shift wraps onto the node itself
+    case = Case(1, 12, 10, jmode="moment", seed=35)
+    _print_case("nx = 1")
+    ny, nz = case.ny, case.nz
+    y = torch.arange(ny, dtype=torch.float64).view(1, ny, 1).expand(nz, ny, 1)
+    z = torch.arange(nz, dtype=torch.float64).view(nz, 1, 1).expand(nz, ny, 1)
+    ky, kz = 2 * math.pi / ny, 2 * math.pi / nz
+    A = 0.02
+    # solenoidal: each component is independent of its own coordinate
+    u = torch.stack([A * torch.sin(ky * y + kz * z), A * torch.cos(kz * z), A * torch.sin(ky * y)])
+    b = torch.stack([A * torch.cos(kz * z), A * torch.sin(2 * kz * z), A * torch.cos(ky * y)])
+    gu = torch.zeros(3, 3, nz, ny, 1, dtype=torch.float64)
+    gb = torch.zeros_like(gu)
+    gu[1, 0] = A * ky * torch.cos(ky * y + kz * z)
+    gu[2, 0] = A * kz * torch.cos(ky * y + kz * z)
+    gu[2, 1] = -A * kz * torch.sin(kz * z)
+    gu[1, 2] = A * ky * torch.cos(ky * y)
+    gb[2, 0] = -A * kz * torch.sin(kz * z)
+    gb[2, 1] = 2 * A * kz * torch.cos(2 * kz * z)
+    gb[1, 2] = -A * ky * torch.sin(ky * y)
+    s = _gpu_from(case, u, gu, b, gb)
+    p = scheme.Params(case.nx, ny, nz, case.nu, case.eta, case.d_i, case.b0, "moment", "closed")
+    st = scheme.step(scheme.init_state(p, u, b, gu, gb), p, 21)
+    s.step(21)
+    assert deviation_error(s, p, st) < 1e-12
