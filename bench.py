@@ -286,7 +286,9 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--size", type=int, default=512)
-    ap.add_argument("--variants", default="all", help="all | headline | stencil (the FP32 stencil kernel alone)")
+    ap.add_argument("--variants", default="all",
+                    help="all | headline | stencil (the FP32 stencil kernel alone) | adjoint (the reverse-mode "
+                         "segments alone, printed as one JSON list)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-copy-probe", action="store_true",
@@ -304,6 +306,10 @@ def main(argv=None):
         from paper_2212_11024_amd.build import build
         build()
     torch.cuda.set_device(0)
+    adjoint_cases = (("moment", "trace"), ("moment", "state"), ("stencil", "state"))
+    if args.variants == "adjoint":
+        print(json.dumps([adjoint_timing(128, "f32", jm, recompute=rc) for jm, rc in adjoint_cases]), flush=True)
+        return 0
     n = args.size
     copy = copy_probe() if (args.copy_probe or (args.variants == "all" and not args.no_copy_probe)) else None
     fields = workload_fields(n, "cuda")
@@ -333,7 +339,7 @@ def main(argv=None):
                                           for f, e in err.items()}
     adj = []
     if args.variants == "all":
-        for jm, rc in (("moment", "trace"), ("moment", "state"), ("stencil", "state")):
+        for jm, rc in adjoint_cases:
             print(f"[bench] adjoint segment 128^3 f32 {jm} ({rc} recompute)", file=sys.stderr, flush=True)
             adj.append(adjoint_timing(128, "f32", jm, recompute=rc))
             print(f"[bench]   {adj[-1]}", file=sys.stderr, flush=True)
