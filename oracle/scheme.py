@@ -30,7 +30,7 @@ import torch
 from . import collision
 from .current import current_moment, current_stencil, divergence_moment
 from .equilibrium import f_mhd_eq, g_eq_hall
-from .lattice import C, CS2, C2, DT, WM, XI, omega_fluid, omega_magnetic
+from .lattice import C, CS2, DT, WM, XI, omega_fluid, omega_magnetic
 
 
 @dataclasses.dataclass

@@ -10,7 +10,7 @@ import torch
 from oracle import collision as col
 from oracle import current as cur
 from oracle.equilibrium import f_mhd_eq
-from oracle.lattice import C, C2, CS2, XI
+from oracle.lattice import C, C2
 
 torch.manual_seed(1)
 

@@ -3,7 +3,6 @@ and the FP64 oracle's rounding floor that it exposes."""
 
 import numpy as np
 import pytest
-import torch
 
 from oracle import extended, scheme
 

@@ -7,7 +7,6 @@ and its first moment).
 
 import itertools
 
-import pytest
 import torch
 
 from oracle import equilibrium as eq

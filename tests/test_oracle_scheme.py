@@ -11,7 +11,7 @@ import torch
 
 import synthetic
 from oracle import analytic, diagnostics, scheme
-from oracle.lattice import C, C2, CS2, XI
+from oracle.lattice import C, C2, CS2
 
 TOL_WAVE = {"stencil": 0.01, "moment": 0.05}
 

@@ -4,7 +4,6 @@ import os
 from fractions import Fraction
 
 import numpy as np
-import torch
 
 import synthetic
 from oracle.lattice import C, C2, W, WM
