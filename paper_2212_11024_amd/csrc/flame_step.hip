@@ -43,10 +43,6 @@ struct StepArgs {
   PhysConst<R> k;
 };
 
-__device__ __forceinline__ size_t node(int x, int y, int z, int nx, int ny) {
-  return (static_cast<size_t>(z) * ny + y) * nx + x;
-}
-
 // Addresses: every population array is indexed from a wave-uniform base (set + q * n, held in
 // scalar registers) by a 32-bit per-lane node offset. A thread's nine in-plane neighbour
 // offsets (x + dx, y + dy) are loop invariants; the plane offset z * nx * ny is uniform.
