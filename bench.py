@@ -37,7 +37,7 @@ HBM_PEAK_GBPS = 8000.0        # MI355X HBM3E peak
 # HBM traffic of the headline kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE passes, calibrated on
 # a plain copy (see the traffic summary named below). Valid only for the kernel source it was
 # measured on: reported as null once the fingerprint of the kernel sources changes.
-TRAFFIC_RECORD = {"fingerprint": "bb2d89634dee8291", "GB_per_launch": 55.33,
+TRAFFIC_RECORD = {"fingerprint": "d44a3f46f0be8647", "GB_per_launch": 55.32,
                   "profile": "profiles/traffic_step_f32_moment_512.md"}
 
 

@@ -27,6 +27,13 @@ __host__ __device__ constexpr int cq(int i, int a) {
 }
 // In the App. A listing the opposite of direction i (1 <= i <= 13) is i + 13.
 __host__ __device__ constexpr int oppq(int i) { return i == 0 ? 0 : (i <= 13 ? i + 13 : i - 13); }
+// Index of the D3Q27 direction (x, y, z) in the App. A order.
+__host__ __device__ constexpr int qindex(int x, int y, int z) {
+  int k = 0;
+  for (int i = 0; i < 27; ++i)
+    if (cq(i, 0) == x && cq(i, 1) == y && cq(i, 2) == z) k = i;
+  return k;
+}
 __host__ __device__ constexpr int speed2q(int i) {
   return cq(i, 0) * cq(i, 0) + cq(i, 1) * cq(i, 1) + cq(i, 2) * cq(i, 2);
 }
@@ -197,7 +204,12 @@ struct Axis {
 // the velocity, the collision sets the first central moment to +F/2).
 // In deviations: f^mhd(0)_i - f_rest_i = w_i [d rho E_i + (E_i - 1)] + (w_i / 2 c_s^4)
 // (M(B) - M(b0)) : (c c - c_s^2 I), E_i = prod_a (1 + e_a), M(B) = |B|^2/2 I - B B.
-template <typename R>
+//
+// Grouped selects the order in which the 27 directions are formed: false, one direction at a time
+// in the App. A order; true, by (c_x, c_y) columns sharing their x/y factors, which shortens live
+// ranges (fewer registers). Both give the same values; the grouped order pays where the step is
+// arithmetic-bound (FP16 storage) and costs write combining in the odd AA step where it is not.
+template <typename R, bool Grouped = false>
 FLAME_HD void collide_fluid(R (&f)[kQ], const FluidMoments<R>& m, R rho,
                                               const R (&U)[3], const R (&b)[3], const R (&b0)[3],
                                               const R (&F)[3], R omega) {
@@ -220,23 +232,53 @@ FLAME_HD void collide_fluid(R (&f)[kQ], const FluidMoments<R>& m, R rho,
             + R(0.5) * (b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
   const Axis<R> ax(U[0]), ay(U[1]), az(U[2]);
   const R drho = m.drho;
+  // each direction: equilibrium deviation w_i [d rho E_i + (E_i - 1)], the Maxwell-stress change,
+  // and the collided second moments and force through the h-factors
+  if constexpr (Grouped) {
 #pragma unroll
-  for (int i = 0; i < kQ; ++i) {
-    const int x = cq(i, 0) + 1, y = cq(i, 1) + 1, z = cq(i, 2) + 1;
-    const R ex = ax.e[x], ey = ay.e[y], ez = az.e[z];
-    const R em1 = ex + (R(1) + ex) * (ey + (R(1) + ey) * ez);   // E_i - 1 without cancellation
-    const R w = R(wq(i));
-    R v = w * (drho * (R(1) + em1) + em1);
-    const R bc = R(cq(i, 0)) * b[0] + R(cq(i, 1)) * b[1] + R(cq(i, 2)) * b[2];
-    const R b0c = R(cq(i, 0)) * b0[0] + R(cq(i, 1)) * b0[1] + R(cq(i, 2)) * b0[2];
-    v += (w * R(4.5)) * (s * R(speed2q(i) - 1.0 / 3.0) - bc * (R(2) * b0c + bc));
-    const R h0x = ax.h0[x], h0y = ay.h0[y], h0z = az.h0[z];
-    const R h1x = ax.h1[x], h1y = ay.h1[y], h1z = az.h1[z];
-    const R h2x = ax.h2[x], h2y = ay.h2[y], h2z = az.h2[z];
-    v += h0z * (h2x * h0y * qxx + h0x * h2y * qyy + h1x * h1y * qxy + h1x * h0y * fhx + h0x * h1y * fhy)
-       + h1z * (h1x * h0y * qxz + h0x * h1y * qyz + h0x * h0y * fhz)
-       + h2z * (h0x * h0y * qzz);
-    f[i] = v;
+    for (int X = 0; X < 3; ++X) {
+#pragma unroll
+      for (int Y = 0; Y < 3; ++Y) {
+        const R h0x = ax.h0[X], h0y = ay.h0[Y], h1x = ax.h1[X], h1y = ay.h1[Y], h2x = ax.h2[X], h2y = ay.h2[Y];
+        const R p00 = h0x * h0y;
+        const R A0 = h2x * h0y * qxx + h0x * h2y * qyy + h1x * h1y * qxy + h1x * h0y * fhx + h0x * h1y * fhy;
+        const R A1 = h1x * h0y * qxz + h0x * h1y * qyz + p00 * fhz;
+        const R A2 = p00 * qzz;
+        const R ex = ax.e[X], ey = ay.e[Y];
+#pragma unroll
+        for (int Z = 0; Z < 3; ++Z) {
+          const int i = qindex(X - 1, Y - 1, Z - 1);
+          const R ez = az.e[Z];
+          const R em1 = ex + (R(1) + ex) * (ey + (R(1) + ey) * ez);   // E_i - 1 without cancellation
+          const R w = R(wq(i));
+          R v = w * (drho * (R(1) + em1) + em1);
+          const R bc = R(cq(i, 0)) * b[0] + R(cq(i, 1)) * b[1] + R(cq(i, 2)) * b[2];
+          const R b0c = R(cq(i, 0)) * b0[0] + R(cq(i, 1)) * b0[1] + R(cq(i, 2)) * b0[2];
+          v += (w * R(4.5)) * (s * R(speed2q(i) - 1.0 / 3.0) - bc * (R(2) * b0c + bc));
+          v += az.h0[Z] * A0 + az.h1[Z] * A1 + az.h2[Z] * A2;
+          f[i] = v;
+        }
+      }
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+      const int x = cq(i, 0) + 1, y = cq(i, 1) + 1, z = cq(i, 2) + 1;
+      const R ex = ax.e[x], ey = ay.e[y], ez = az.e[z];
+      const R em1 = ex + (R(1) + ex) * (ey + (R(1) + ey) * ez);   // E_i - 1 without cancellation
+      const R w = R(wq(i));
+      R v = w * (drho * (R(1) + em1) + em1);
+      const R bc = R(cq(i, 0)) * b[0] + R(cq(i, 1)) * b[1] + R(cq(i, 2)) * b[2];
+      const R b0c = R(cq(i, 0)) * b0[0] + R(cq(i, 1)) * b0[1] + R(cq(i, 2)) * b0[2];
+      v += (w * R(4.5)) * (s * R(speed2q(i) - 1.0 / 3.0) - bc * (R(2) * b0c + bc));
+      const R h0x = ax.h0[x], h0y = ay.h0[y], h0z = az.h0[z];
+      const R h1x = ax.h1[x], h1y = ay.h1[y], h1z = az.h1[z];
+      const R h2x = ax.h2[x], h2y = ay.h2[y], h2z = az.h2[z];
+      v += h0z * (h2x * h0y * qxx + h0x * h2y * qyy + h1x * h1y * qxy + h1x * h0y * fhx + h0x * h1y * fhy)
+         + h1z * (h1x * h0y * qxz + h0x * h1y * qyz + h0x * h0y * fhz)
+         + h2z * (h0x * h0y * qzz);
+      f[i] = v;
+    }
   }
 }
 

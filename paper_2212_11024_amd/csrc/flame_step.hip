@@ -161,14 +161,14 @@ __device__ __forceinline__ void forcing_at(const StepArgs<S>& a, uint32_t cell, 
 }
 
 // Node update from loaded populations and J: moments, both collisions, in place in f and g.
-template <typename R>
+template <bool Grouped, typename R>
 __device__ __forceinline__ void collide_node(R (&f)[kQ], R (&g)[kM], const FluidMoments<R>& m, const R (&U)[3],
                                              const R (&b)[3], const R (&J)[3], const R (&F)[3], const R (&Sb)[3],
                                              const PhysConst<R>& k) {
   const R rho = R(1) + m.drho;
   const R b0[3] = {k.b0[0], k.b0[1], k.b0[2]};
   const R B[3] = {b0[0] + b[0], b0[1] + b[1], b0[2] + b[2]};
-  collide_fluid(f, m, rho, U, b, b0, F, k.omega);
+  collide_fluid<R, Grouped>(f, m, rho, U, b, b0, F, k.omega);
   collide_magnetic(g, U, B, b, J, Sb, k.alpha, k.omega_b);
 }
 
@@ -219,7 +219,7 @@ __global__ __launch_bounds__(kLocalThreads) void step_local(StepArgs<S> a) {
   R J[3];
   current_from_moments(lam, U, B, a.k.alpha, a.k.omega_b, J);
   if (SAVE) save_current(a.save, a.n, cell, J);
-  collide_node(f, g, m, U, b, J, F, Sb, a.k);
+  collide_node<sizeof(S) == 2>(f, g, m, U, b, J, F, Sb, a.k);
   store_fluid<S, FAA, PAR>(a, rw, pl, f);
   store_magnetic<S, MAA, PAR>(a, rw, pl, g);
 }

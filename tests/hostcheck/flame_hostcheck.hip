@@ -20,8 +20,9 @@ PhysConst<double> consts(const double* p) {
 extern "C" {
 
 // One node's collision on deviations. params = {omega, omega_b, alpha, b0x, b0y, b0z}.
-// moment != 0: J from the moments (J_in ignored); else J = J_in. J_out receives the J used.
-void hc_collide(int moment, const double* f_in, const double* g_in, const double* Fin, const double* Sin,
+// mode bit 0 set: J from the moments (J_in ignored); else J = J_in. J_out receives the J used.
+// mode bit 1 set: the fluid directions formed in the grouped (c_x, c_y) order.
+void hc_collide(int mode, const double* f_in, const double* g_in, const double* Fin, const double* Sin,
                 const double* J_in, const double* params, double* f_out, double* g_out, double* J_out) {
   const PhysConst<double> k = consts(params);
   double f[kQ], g[kM], F[3], S[3];
@@ -36,10 +37,11 @@ void hc_collide(int moment, const double* f_in, const double* g_in, const double
   for (int c = 0; c < 3; ++c) b[c] += 0.5 * S[c];
   const double B[3] = {k.b0[0] + b[0], k.b0[1] + b[1], k.b0[2] + b[2]};
   double J[3];
-  if (moment) current_from_moments(lam, U, B, k.alpha, k.omega_b, J);
+  if (mode & 1) current_from_moments(lam, U, B, k.alpha, k.omega_b, J);
   else for (int c = 0; c < 3; ++c) J[c] = J_in[c];
   const double b0[3] = {k.b0[0], k.b0[1], k.b0[2]};
-  collide_fluid(f, m, rho, U, b, b0, F, k.omega);
+  if (mode & 2) collide_fluid<double, true>(f, m, rho, U, b, b0, F, k.omega);
+  else collide_fluid<double, false>(f, m, rho, U, b, b0, F, k.omega);
   collide_magnetic(g, U, B, b, J, S, k.alpha, k.omega_b);
   for (int i = 0; i < kQ; ++i) f_out[i] = f[i];
   for (int i = 0; i < kM; ++i) g_out[i] = g[i];

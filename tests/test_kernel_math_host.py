@@ -77,8 +77,9 @@ def _oracle_node(f, g, F, S, params, J=None):
     return fs.reshape(27), gs.reshape(21)
 
 
+@pytest.mark.parametrize("grouped", [0, 1])
 @pytest.mark.parametrize("moment", [1, 0])
-def test_forward_collision_matches_oracle(hc, moment):
+def test_forward_collision_matches_oracle(hc, moment, grouped):
     rng = np.random.default_rng(10 + moment)
     for _ in range(20):
         params, rest, f, g, F, S, J, kp = _case(rng)
@@ -88,7 +89,7 @@ def test_forward_collision_matches_oracle(hc, moment):
         fo, pfo = _p(np.zeros(27))
         go, pgo = _p(np.zeros(21))
         jo, pjo = _p(np.zeros(3))
-        hc.hc_collide(moment, pdf, pdg, _p(F)[1], _p(S)[1], _p(J)[1], _p(kp)[1], pfo, pgo, pjo)
+        hc.hc_collide(moment | (grouped << 1), pdf, pdg, _p(F)[1], _p(S)[1], _p(J)[1], _p(kp)[1], pfo, pgo, pjo)
         t = lambda a: torch.tensor(a, dtype=torch.float64)  # noqa: E731
         ofs, ogs = _oracle_node(t(f), t(g), t(F), t(S), params, None if moment else t(J))
         assert np.abs(fo - (ofs.numpy() - fr)).max() < 1e-15
