@@ -148,6 +148,16 @@ flame_status flame_reduce(flame_ctx* c, double* out);
  * wavevector (paper Sec. 4.4 spectra). FP64 FFT (hipFFT) and binning. Synchronises. */
 flame_status flame_spectrum(flame_ctx* c, int32_t field, int32_t nshells, double* e_k);
 
+/* Shell dissipation spectrum of u (field = 0) or B (field = 1) into host d_k[nshells]:
+ * D(s) = sum_{round(|k|) = s} |q(k)|^2 |v_hat(k)|^2, q_a = 2 pi k_a / n_a in inverse cells, the
+ * summand of the dissipation D(k) of the paper's scale-by-scale energy budget (Sec. 4.4, eq.
+ * mhd_en_trans) without the factor nu or eta. sum_s D(s) = <|grad v|^2> (Parseval), which is
+ * <|curl v|^2> for a solenoidal field, so nu sum D_u + eta sum D_B is the dissipation rate of
+ * the energy 1/2 <|u|^2 + |B|^2>. Same transform, shells, errors (FLAME_E_INVAL for a field
+ * other than 0 or 1, nshells outside 1..4096 or a NULL d_k) and synchronisation as
+ * flame_spectrum. */
+flame_status flame_dissipation_spectrum(flame_ctx* c, int32_t field, int32_t nshells, double* d_k);
+
 /* Copy the state in canonical order to / from device double dst/src [48 * ncell].
  * deviations = 0: full population values; deviations = 1: departures from the rest state of
  * flame_rest_populations, which are the stored values exactly (decoded), so a get / set pair

@@ -10,6 +10,12 @@ div B is the moment estimate -(w_B / C^2) Tr Lambda.
 
 Spectrum of a vector field v on an n^3 grid: E(s) = 1/2 sum_{round(|k|) = s} |v_hat(k)|^2 with
 v_hat = DFT(v) / n^3 and k the signed integer wavevector; by Parseval sum_s E(s) = 1/2 <|v|^2>.
+
+Dissipation spectrum (the summand of D(k) in Sec. 4.4, eq. mhd_en_trans, without the factor nu
+or eta): D(s) = sum_{round(|k|) = s} |q(k)|^2 |v_hat(k)|^2, with q_a = 2 pi k_a / n_a the
+wavevector in inverse cells; sum_s D(s) = <|grad v|^2> of the grid's trigonometric interpolant,
+which is <|curl v|^2> when v is solenoidal. The dissipation rate of the energy 1/2 <|u|^2 + |B|^2>
+is then nu sum_s D_u(s) + eta sum_s D_B(s).
 """
 
 import math
@@ -63,6 +69,23 @@ def spectrum(v, nshells):
         vh = np.fft.fftn(arr[b]) / n
         e += np.bincount(s.ravel(), weights=0.5 * np.abs(vh.ravel()) ** 2, minlength=nshells)[:nshells]
     return e
+
+
+def dissipation_spectrum(v, nshells):
+    """Shell dissipation spectrum of a (3, nz, ny, nx) real field; shells 0..nshells-1."""
+    arr = v.detach().cpu().numpy() if torch.is_tensor(v) else np.asarray(v)
+    nz, ny, nx = arr.shape[1:]
+    n = arr[0].size
+    qz = 2 * np.pi * np.fft.fftfreq(nz, 1.0 / nz) / nz
+    qy = 2 * np.pi * np.fft.fftfreq(ny, 1.0 / ny) / ny
+    qx = 2 * np.pi * np.fft.fftfreq(nx, 1.0 / nx) / nx
+    q2 = qz[:, None, None] ** 2 + qy[None, :, None] ** 2 + qx[None, None, :] ** 2
+    d = np.zeros(nshells)
+    s = shell_index(arr.shape[1:])
+    for b in range(3):
+        vh = np.fft.fftn(arr[b]) / n
+        d += np.bincount(s.ravel(), weights=(q2 * np.abs(vh) ** 2).ravel(), minlength=nshells)[:nshells]
+    return d
 
 
 def max_shell(shape):

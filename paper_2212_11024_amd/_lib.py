@@ -48,6 +48,8 @@ _SIGNATURES = {
     "flame_moments": (ctypes.c_int32, [_P, _P, _P, _P, _P, _P]),
     "flame_reduce": (ctypes.c_int32, [_P, ctypes.POINTER(ctypes.c_double)]),
     "flame_spectrum": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
+    "flame_dissipation_spectrum": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32,
+                                                    ctypes.POINTER(ctypes.c_double)]),
     "flame_get_populations": (ctypes.c_int32, [_P, _P, ctypes.c_int32]),
     "flame_set_populations": (ctypes.c_int32, [_P, _P, ctypes.c_int32]),
     "flame_gather": (ctypes.c_int32, [_P, _P, ctypes.c_int64, _P, ctypes.c_int32]),
@@ -140,6 +142,12 @@ def flame_reduce(ctx: int, allow_nonfinite: bool = False):
 def flame_spectrum(ctx: int, field: int, nshells: int):
     out = (ctypes.c_double * nshells)()
     _check(load().flame_spectrum(ctx, field, nshells, out), ctx)
+    return list(out)
+
+
+def flame_dissipation_spectrum(ctx: int, field: int, nshells: int):
+    out = (ctypes.c_double * nshells)()
+    _check(load().flame_dissipation_spectrum(ctx, field, nshells, out), ctx)
     return list(out)
 
 

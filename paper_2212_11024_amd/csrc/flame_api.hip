@@ -443,9 +443,11 @@ constexpr int kSpecShellsMax = 4096;
 __device__ __forceinline__ int signed_freq(int idx, int n) { return idx <= (n - 1) / 2 ? idx : idx - n; }
 
 // Half-spectrum (nz, ny, nx/2+1) of an r2c transform; each entry stands for itself and, for
-// 0 < kx < nx - kx, its conjugate mirror at -k (same shell).
+// 0 < kx < nx - kx, its conjugate mirror at -k (same shell). Each entry adds w |X|^2 norm2 to
+// its shell: w = 1/2 for the energy spectrum; w = |q|^2, q_a = 2 pi k_a / n_a, for the
+// dissipation spectrum (k2 set).
 __global__ __launch_bounds__(kSpecThreads) void shell_bin_kernel(const hipfftDoubleComplex* X, int nx, int ny,
-                                                                 int nz, int nshells, double norm2,
+                                                                 int nz, int nshells, double norm2, int k2,
                                                                  double* partials) {
   extern __shared__ double bins[];
   for (int s = threadIdx.x; s < nshells; s += blockDim.x) bins[s] = 0.0;
@@ -463,7 +465,12 @@ __global__ __launch_bounds__(kSpecThreads) void shell_bin_kernel(const hipfftDou
     if (shell >= nshells) continue;
     const double re = X[k].x, im = X[k].y;
     const double mult = (kx == 0 || 2 * kx == nx) ? 1.0 : 2.0;
-    atomicAdd(&bins[shell], mult * 0.5 * (re * re + im * im) * norm2);
+    double w = 0.5;
+    if (k2) {
+      const double qx = (2.0 * M_PI / nx) * fx, qy = (2.0 * M_PI / ny) * fy, qz = (2.0 * M_PI / nz) * fz;
+      w = qx * qx + qy * qy + qz * qz;
+    }
+    atomicAdd(&bins[shell], mult * w * (re * re + im * im) * norm2);
   }
   __syncthreads();
   for (int s = threadIdx.x; s < nshells; s += blockDim.x) partials[static_cast<size_t>(blockIdx.x) * nshells + s] = bins[s];
@@ -813,7 +820,12 @@ flame_status flame_reduce(flame_ctx* c, double* out) {
   return FLAME_OK;
 }
 
-flame_status flame_spectrum(flame_ctx* c, int32_t field, int32_t nshells, double* e_k) {
+}  // extern "C"
+
+namespace {
+
+// Energy (k2 = 0) or dissipation (k2 = 1) shell spectrum of u or B, summed over components.
+flame_status shell_spectrum(flame_ctx* c, int32_t field, int32_t nshells, int k2, double* e_k) {
   if (!c) return FLAME_E_INVAL;
   if (field != 0 && field != 1) return fail(c, FLAME_E_INVAL, "field must be 0 (u) or 1 (B)");
   if (nshells < 1 || nshells > kSpecShellsMax) return fail(c, FLAME_E_INVAL, "nshells out of range");
@@ -852,7 +864,7 @@ flame_status flame_spectrum(flame_ctx* c, int32_t field, int32_t nshells, double
     if (hipfftExecD2Z(c->plan, c->spec_real, static_cast<hipfftDoubleComplex*>(c->spec_cplx)) != HIPFFT_SUCCESS)
       return fail(c, FLAME_E_HIP, "hipfftExecD2Z failed");
     hipLaunchKernelGGL(shell_bin_kernel, dim3(blocks), dim3(kSpecThreads), sizeof(double) * nshells, c->stream,
-                       static_cast<const hipfftDoubleComplex*>(c->spec_cplx), nx, ny, nz, nshells, norm2,
+                       static_cast<const hipfftDoubleComplex*>(c->spec_cplx), nx, ny, nz, nshells, norm2, k2,
                        c->spec_partials);
     e = hipGetLastError();
     if (e == hipSuccess)
@@ -863,6 +875,18 @@ flame_status flame_spectrum(flame_ctx* c, int32_t field, int32_t nshells, double
       for (int s = 0; s < nshells; ++s) e_k[s] += host[static_cast<size_t>(blk) * nshells + s];
   }
   return FLAME_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+flame_status flame_spectrum(flame_ctx* c, int32_t field, int32_t nshells, double* e_k) {
+  return shell_spectrum(c, field, nshells, 0, e_k);
+}
+
+flame_status flame_dissipation_spectrum(flame_ctx* c, int32_t field, int32_t nshells, double* d_k) {
+  return shell_spectrum(c, field, nshells, 1, d_k);
 }
 
 flame_status flame_get_populations(flame_ctx* c, double* dst, int32_t deviations) {

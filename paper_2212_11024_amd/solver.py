@@ -98,6 +98,13 @@ class Solver:
         return torch.tensor(L.flame_spectrum(self.ctx, {"u": 0, "B": 1}.get(field, field), nshells),
                             dtype=torch.float64)
 
+    def dissipation_spectrum(self, field, nshells):
+        """Per shell sum of |q|^2 |v_hat|^2 (q in inverse cells): nu times its sum over shells is
+        the viscous dissipation rate of 1/2 <|u|^2> (field "u"), eta times it the resistive one
+        (field "B")."""
+        return torch.tensor(L.flame_dissipation_spectrum(self.ctx, {"u": 0, "B": 1}.get(field, field), nshells),
+                            dtype=torch.float64)
+
     # -- canonical state
     def get_populations(self, deviations=False):
         """(f (27, nz, ny, nx), g (7, 3, nz, ny, nx)) float64 on device: full values, or the

@@ -6,7 +6,7 @@ arithmetic: it only draws random numbers, builds mode lists and samples them on 
 """
 
 from .fields import (ModeField, half_space_wavevectors, shell_field, wave_field,
-                     xia_field, scaled, evaluate, evaluate_numpy)
+                     xia_field, orszag_tang, scaled, evaluate, evaluate_numpy)
 
 __all__ = ["ModeField", "half_space_wavevectors", "shell_field", "wave_field", "xia_field",
-           "scaled", "evaluate", "evaluate_numpy"]
+           "orszag_tang", "scaled", "evaluate", "evaluate_numpy"]

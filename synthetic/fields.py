@@ -12,6 +12,8 @@ Recipes (see the design notes for the workloads they stand in for):
     numpy's PCG64 generator from a seed, rescaled to a given rms of |f|.
   * wave_field: the circularly polarised plane wave a (sin kz, cos kz, 0).
   * xia_field: the three-mode Beltrami field of the paper's validation runs (Sec. 4.1).
+  * orszag_tang: the Orszag-Tang vortex velocity and magnetic field of the paper's comparison
+    with a pseudo-spectral code and of its Hall-MHD runs (Sec. 4.4, Sec. 5).
 """
 
 from __future__ import annotations
@@ -108,6 +110,27 @@ def xia_field(u0: float, a: float = 0.3, b: float = 0.2, c: float = 0.1, kidx: i
                              [a, 0.0, -1j * a],
                              [0.0, -1j * c, c]], dtype=np.complex128)
     return ModeField(k, v)
+
+
+def orszag_tang(u_amp: float, b_amp: float) -> tuple[ModeField, ModeField]:
+    """Orszag-Tang vortex on a box of 2 pi per axis (Sec. 4.4), with X = 2 pi x / n per axis:
+
+    u = u_amp (-2 sin Y, 2 sin X, 0),
+    B = b_amp (-2 sin 2Y + sin Z, 2 sin X + sin Z, sin X + sin Y).
+
+    Both are solenoidal; <|u|^2> = 4 u_amp^2, <|B|^2> = 6 b_amp^2, <u . B> = 2 u_amp b_amp.
+    Uses sin t = 2 Re[(-i/2) e^{i t}] on the modes (1,0,0), (0,1,0), (0,2,0), (0,0,1).
+    """
+    h = -0.5j
+    ku = np.array([[1, 0, 0], [0, 1, 0]], dtype=np.int64)
+    vu = u_amp * np.array([[0.0, 2 * h, 0.0],
+                           [-2 * h, 0.0, 0.0]], dtype=np.complex128)
+    kb = np.array([[1, 0, 0], [0, 1, 0], [0, 2, 0], [0, 0, 1]], dtype=np.int64)
+    vb = b_amp * np.array([[0.0, 2 * h, h],
+                           [0.0, 0.0, h],
+                           [-2 * h, 0.0, 0.0],
+                           [h, h, 0.0]], dtype=np.complex128)
+    return ModeField(ku, vu), ModeField(kb, vb)
 
 
 def scaled(f: ModeField, s: float) -> ModeField:

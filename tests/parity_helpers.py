@@ -27,6 +27,7 @@ class Case:
     forced: bool = False
     seed: int = 0
     kmax: int = 2
+    ic: str = "shell"      # "shell": seeded shell fields; "orszag_tang": u amplitude rms, B amplitude 0.8 rms
 
     @property
     def shape(self):
@@ -35,9 +36,14 @@ class Case:
 
 def inputs(case: Case, device="cpu"):
     """u, grad u, b, grad b, F, S (float64) on ``device``; F, S are None when unforced."""
-    km = min(case.kmax, (min(case.shape) - 1) // 2)
-    u, gu = synthetic.evaluate(synthetic.shell_field(case.seed, 1, km, case.rms), case.shape, device)
-    b, gb = synthetic.evaluate(synthetic.shell_field(case.seed + 1, 1, km, case.rms), case.shape, device)
+    if case.ic == "orszag_tang":
+        fu_ic, fb_ic = synthetic.orszag_tang(case.rms, 0.8 * case.rms)
+    else:
+        km = min(case.kmax, (min(case.shape) - 1) // 2)
+        fu_ic = synthetic.shell_field(case.seed, 1, km, case.rms)
+        fb_ic = synthetic.shell_field(case.seed + 1, 1, km, case.rms)
+    u, gu = synthetic.evaluate(fu_ic, case.shape, device)
+    b, gb = synthetic.evaluate(fb_ic, case.shape, device)
     fu = fb = None
     if case.forced:
         fu, _ = synthetic.evaluate(synthetic.shell_field(case.seed + 2, 0, 1, 1e-4, "radius"), case.shape, device,

@@ -1,0 +1,126 @@
+"""The Orszag-Tang vortex, the initial condition of the paper's turbulence runs (Sec. 4.4, Sec. 5):
+time series of the energies and of the dissipation rate, and the energy budget they must close.
+
+Lattice units: u amplitude U0 = Ma / sqrt(3) with Ma = 0.025 (the Mach number of the paper's
+comparison with a pseudo-spectral code), B amplitude 0.8 U0, b0 = 0, rho = 1, reference time
+tau0 = (n / 2 pi) / U0 (the box is 2 pi reference lengths), nu = eta from the initial Reynolds
+number Re0 = 2 U0 n / nu (initial rms velocity 2 U0, box length n).
+
+Energy budget. In incompressible MHD the energy E = 1/2 <|u|^2 + |B|^2> changes only by
+dissipation, dE/dt = -eps with eps = nu <|grad u|^2> + eta <|grad B|^2>, which is nu sum D_u +
+eta sum D_B over the dissipation spectra; the Hall term conserves E (J . (J x B) = 0). The
+lattice scheme adds two effects, both removing energy from E: the start (rho = 1) is not in
+pressure balance, so sound takes up and exchanges back an energy of the order of the squared rms
+Mach number times E, (2 Ma)^2 E(0); and the scheme's own dissipation exceeds nu k^2 at second
+order in k dx (3% at 24^3 in the oracle, falling as n^-2). The missing energy
+E(0) - E(t) - int_0^t eps dt is therefore positive and below 4 Ma^2 E(0) + 0.02 int_0^t eps dt at
+every sample (measured: the sound share peaks near 2.5 Ma^2 E(0) early on; at the end of the
+runs the missing energy is 0.8-1.0% of int eps at 64^3 and 512^3).
+
+FP32 storage against FP64: a 2^-24 rounding of the stored deviations per step random-walks to
+6e-8 sqrt(S) of the velocity after S steps, 2 x that in E; over S = 1412 steps (2 tau0 at 64^3)
+that is 4.5e-6, and the bar takes a factor 10 (the flow at Re0 = 200 is laminar-to-transitional
+over this time, so it does not amplify the difference much).
+
+The 512^3 FP64 run to beyond the dissipation peak is opt-in (FLAME_LARGE=1). Its Re0 = 3200 is
+chosen for a Reynolds number near 1600 at the peak, that of the paper's comparison run: the runs
+at 64^3 to 256^3 reach about Re0 / 2 there."""
+
+import math
+import os
+
+import pytest
+import torch
+
+import synthetic
+
+pytestmark = pytest.mark.gpu
+
+MA = 0.025
+
+
+def ot_run(n, storage, re0, eps_h, tau_end, samples, log=None):
+    """Run the Orszag-Tang vortex on n^3 to tau_end reference times; (params, rows) with rows of
+    (step, t / tau0, E, eps, E_kin, E_mag, <|J|^2>, non-finite nodes, Re). Re = u_rms L / nu with
+    u_rms = <|u|^2>^(1/2) and the integral scale L = n sum_s E_u(s) / s / sum_s E_u(s) in cells
+    (Sec. 4.4, with the box of n cells as 2 pi reference lengths)."""
+    from paper_2212_11024_amd.solver import Solver
+    u0 = MA / math.sqrt(3.0)
+    nu = 2.0 * u0 * n / re0
+    tau0 = (n / (2.0 * math.pi)) / u0
+    fu, fb = synthetic.orszag_tang(u0, 0.8 * u0)
+    u, gu = synthetic.evaluate(fu, (n, n, n), "cuda")
+    b, gb = synthetic.evaluate(fb, (n, n, n), "cuda")
+    s = Solver(n, n, n, nu, nu, eps_h * n, (0.0, 0.0, 0.0), storage, "moment", "aa", u, b, gu, gb)
+    del u, gu, b, gb
+    torch.cuda.empty_cache()
+    ns = n // 2 + 1
+    every = max(1, int(round(tau_end * tau0 / samples)))
+    rows = []
+    for i in range(samples + 1):
+        red = s.reduce(allow_nonfinite=True)
+        eps = nu * float(s.dissipation_spectrum("u", ns).sum() + s.dissipation_spectrum("B", ns).sum())
+        eu = s.spectrum("u", ns)[1:]
+        scale = n * float((eu / torch.arange(1, ns, dtype=eu.dtype)).sum() / eu.sum())
+        re = math.sqrt(2.0 * float(red[0])) * scale / nu
+        rows.append((i * every, i * every / tau0, float(red[0] + red[1]), eps, float(red[0]), float(red[1]),
+                     float(red[3]), int(red[8]), re))
+        if log:
+            log(rows[-1])
+        if i < samples:
+            s.step(every)
+    s.close()
+    return {"nu": nu, "tau0": tau0, "every": every}, rows
+
+
+def budget(rows):
+    """(t / tau0, missing energy E(0) - E(t) - int_0^t eps dt, int_0^t eps dt) at every sample
+    after the first, with the trapezoid rule between samples."""
+    out, integral = [], 0.0
+    for a, b in zip(rows, rows[1:]):
+        integral += 0.5 * (a[3] + b[3]) * (b[0] - a[0])
+        out.append((b[1], rows[0][2] - b[2] - integral, integral))
+    return out
+
+
+def check_budget(rows, tag):
+    e0 = rows[0][2]
+    ratios = []
+    for t, missing, integral in budget(rows):
+        assert 0.0 < missing < 4.0 * MA * MA * e0 + 0.02 * integral, (t, missing, integral)
+        ratios.append(missing / integral)
+    print(f"[{tag}] missing energy / int eps: {ratios[len(ratios) // 4]:.4f} at a quarter of the run, "
+          f"{ratios[-1]:.4f} at the end", flush=True)
+
+
+@pytest.mark.parametrize("eps_h", [0.0, 0.01])
+def test_energy_budget_closes_64(eps_h):
+    print(f"[orszag-tang] 64^3 FP64 and FP32, Re0 = 200, eps_h = {eps_h}, 2 tau0", flush=True)
+    runs = {st: ot_run(64, st, 200.0, eps_h, 2.0, 40) for st in ("f64", "f32")}
+    for st, (prm, rows) in runs.items():
+        assert all(r[7] == 0 for r in rows)
+        assert rows[-1][2] < 0.6 * rows[0][2]          # the vortex decays
+        check_budget(rows, f"orszag-tang {st}")
+    e64 = torch.tensor([r[2] for r in runs["f64"][1]])
+    e32 = torch.tensor([r[2] for r in runs["f32"][1]])
+    rel = float(((e32 - e64).abs() / e64).max())
+    print(f"[orszag-tang]   FP32 vs FP64 energy: max relative {rel:.2e}", flush=True)
+    assert rel < 4.5e-5
+
+
+@pytest.mark.skipif(os.environ.get("FLAME_LARGE") != "1", reason="opt-in 512^3 run (FLAME_LARGE=1)")
+def test_orszag_tang_512_to_dissipation_peak():
+    n = 512
+    print("[orszag-tang] 512^3 FP64, Re0 = 3200, d_i = 0, to 3 tau0", flush=True)
+
+    def log(r):
+        print(f"[orszag-tang 512] step {r[0]} t/tau0 {r[1]:.3f} E {r[2]:.6e} eps {r[3]:.6e} E_kin {r[4]:.6e} "
+              f"E_mag {r[5]:.6e} <J^2> {r[6]:.6e} bad {r[7]} Re {r[8]:.0f}", flush=True)
+
+    prm, rows = ot_run(n, "f64", 3200.0, 0.0, 3.0, 60, log)
+    assert all(r[7] == 0 for r in rows)
+    peak = max(rows, key=lambda r: r[3])
+    print(f"[orszag-tang 512] nu {prm['nu']:.4e} tau0 {prm['tau0']:.1f} steps; dissipation peak at "
+          f"t/tau0 = {peak[1]:.3f}, eps = {peak[3]:.4e}, Re = {peak[8]:.0f}", flush=True)
+    check_budget(rows, "orszag-tang 512")
+    assert 0 < peak[1] < 3.0 - 1e-9                      # the peak lies inside the run

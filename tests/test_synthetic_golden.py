@@ -58,3 +58,39 @@ def test_seed_determinism():
     b = synthetic.shell_field(7, 1, 4, 0.02)
     assert np.array_equal(a.v, b.v) and np.array_equal(a.k, b.k)
     assert not np.array_equal(a.v, synthetic.shell_field(8, 1, 4, 0.02).v)
+
+
+def test_orszag_tang_fields_match_the_printed_formulas():
+    """Sec. 4.4: u = U0 (-2 sin y, 2 sin x, 0), B = B0 (-2 sin 2y + sin z, 2 sin x + sin z,
+    sin x + sin y) on a 2 pi box; checked against the formulas written with numpy's sin/cos at
+    every node of a non-cubic grid, with the derivatives, mean squares and cross-helicity."""
+    u0, b0 = 0.7, 0.8 * 0.7
+    fu, fb = synthetic.orszag_tang(u0, b0)
+    shape = (10, 12, 14)
+    nx, ny, nz = shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    X, Y, Z = 2 * np.pi * x / nx, 2 * np.pi * y / ny, 2 * np.pi * z / nz
+    qx, qy, qz = 2 * np.pi / nx, 2 * np.pi / ny, 2 * np.pi / nz
+    u_ref = u0 * np.stack([-2 * np.sin(Y), 2 * np.sin(X), 0 * X])
+    b_ref = b0 * np.stack([-2 * np.sin(2 * Y) + np.sin(Z), 2 * np.sin(X) + np.sin(Z), np.sin(X) + np.sin(Y)])
+    zero = 0 * X
+    du_ref = u0 * np.stack([  # [a, b] = d u_b / d x_a
+        np.stack([zero, 2 * qx * np.cos(X), zero]),
+        np.stack([-2 * qy * np.cos(Y), zero, zero]),
+        np.stack([zero, zero, zero])])
+    db_ref = b0 * np.stack([
+        np.stack([zero, 2 * qx * np.cos(X), qx * np.cos(X)]),
+        np.stack([-4 * qy * np.cos(2 * Y), zero, qy * np.cos(Y)]),
+        np.stack([qz * np.cos(Z), qz * np.cos(Z), zero])])
+    for f, ref, dref in ((fu, u_ref, du_ref), (fb, b_ref, db_ref)):
+        v, g = synthetic.evaluate(f, shape)
+        assert np.abs(v.numpy() - ref).max() < 1e-14
+        assert np.abs(g.numpy() - dref).max() < 1e-14
+        pts = np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1)[::37]
+        assert np.abs(synthetic.evaluate_numpy(f, pts, shape) - ref.reshape(3, -1).T[::37]).max() < 1e-14
+    assert abs(fu.mean_square - 4 * u0 ** 2) < 1e-15
+    assert abs(fb.mean_square - 6 * b0 ** 2) < 1e-15
+    assert abs((u_ref * b_ref).sum(0).mean() - 2 * u0 * b0) < 1e-15
+    # solenoidal on any box: each component is independent of its own coordinate
+    for dref in (du_ref, db_ref):
+        assert np.abs(dref[0, 0] + dref[1, 1] + dref[2, 2]).max() == 0.0
