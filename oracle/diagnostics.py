@@ -16,6 +16,14 @@ or eta): D(s) = sum_{round(|k|) = s} |q(k)|^2 |v_hat(k)|^2, with q_a = 2 pi k_a 
 wavevector in inverse cells; sum_s D(s) = <|grad v|^2> of the grid's trigonometric interpolant,
 which is <|curl v|^2> when v is solenoidal. The dissipation rate of the energy 1/2 <|u|^2 + |B|^2>
 is then nu sum_s D_u(s) + eta sum_s D_B(s).
+
+Energy transfer (the summands of the flux S_MHD(k) in Sec. 4.4, per shell s):
+  T_adv(s) = sum Re[u_hat* . F(U . grad U)],  T_lor(s) = -sum Re[u_hat* . F(J x B)],
+  T_ind(s) = -sum Re[B_hat* . F(curl(U x B))],
+so that S_MHD(k) = sum_{s < k} (T_adv + T_lor + T_ind) and, for incompressible MHD without the
+Hall and pressure terms, d/dt sum_{s < k} E(s) = -S_MHD(k) - D(k). Derivatives are spectral with
+q_a = 2 pi k_a / n_a, except that q_a = 0 on the Nyquist index of an even axis (that mode's
+derivative is not a real field). Products are formed node by node on the grid.
 """
 
 import math
@@ -86,6 +94,44 @@ def dissipation_spectrum(v, nshells):
         vh = np.fft.fftn(arr[b]) / n
         d += np.bincount(s.ravel(), weights=(q2 * np.abs(vh) ** 2).ravel(), minlength=nshells)[:nshells]
     return d
+
+
+def derivative_wavenumbers(n):
+    """2 pi k / n for the signed DFT index k of an axis of n nodes; 0 at the Nyquist index."""
+    q = 2.0 * np.pi * np.fft.fftfreq(n, 1.0 / n) / n
+    if n % 2 == 0:
+        q[n // 2] = 0.0
+    return q
+
+
+def energy_transfer(U, B, J, nshells):
+    """(T_adv, T_lor, T_ind), each (nshells,), of (3, nz, ny, nx) real fields U, B and J."""
+    U, B, J = [x.detach().cpu().numpy() if torch.is_tensor(x) else np.asarray(x) for x in (U, B, J)]
+    nz, ny, nx = U.shape[1:]
+    ncell = U[0].size
+    Q = (derivative_wavenumbers(nx)[None, None, :], derivative_wavenumbers(ny)[None, :, None],
+         derivative_wavenumbers(nz)[:, None, None])
+    shell = shell_index(U.shape[1:]).ravel()
+    hat = lambda v: np.fft.fftn(v) / ncell  # noqa: E731
+
+    def binned(values):
+        return np.bincount(shell, weights=values.ravel(), minlength=nshells)[:nshells]
+
+    Uh = [hat(U[b]) for b in range(3)]
+    Bh = [hat(B[b]) for b in range(3)]
+    # (U . grad) U with grad U_b = inverse DFT of i q_a u_hat_b
+    adv = [sum(U[a] * np.real(np.fft.ifftn(1j * Q[a] * np.fft.fftn(U[b]))) for a in range(3)) for b in range(3)]
+    lor = np.cross(J, B, axis=0)
+    W = np.cross(U, B, axis=0)
+    Wh = [hat(W[b]) for b in range(3)]
+    t_adv = sum(binned(np.real(np.conj(Uh[b]) * hat(adv[b]))) for b in range(3))
+    t_lor = -sum(binned(np.real(np.conj(Uh[b]) * hat(lor[b]))) for b in range(3))
+    t_ind = np.zeros(nshells)
+    for b in range(3):
+        c, d = (b + 1) % 3, (b + 2) % 3
+        curl_b = 1j * (Q[c] * Wh[d] - Q[d] * Wh[c])
+        t_ind -= binned(np.real(np.conj(Bh[b]) * curl_b))
+    return t_adv, t_lor, t_ind
 
 
 def max_shell(shape):

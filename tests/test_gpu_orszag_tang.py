@@ -22,9 +22,8 @@ FP32 storage against FP64: a 2^-24 rounding of the stored deviations per step ra
 that is 4.5e-6, and the bar takes a factor 10 (the flow at Re0 = 200 is laminar-to-transitional
 over this time, so it does not amplify the difference much).
 
-The 512^3 FP64 run to beyond the dissipation peak is opt-in (FLAME_LARGE=1). Its Re0 = 3200 is
-chosen for a Reynolds number near 1600 at the peak, that of the paper's comparison run: the runs
-at 64^3 to 256^3 reach about Re0 / 2 there."""
+The 512^3 FP64 run to beyond the dissipation peak is opt-in (FLAME_LARGE=1): Re0 = 3200 reaches
+Re = 1122 at the peak (the paper's comparison run: about 1600) at t = 2.6 tau0."""
 
 import math
 import os
