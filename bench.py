@@ -179,11 +179,24 @@ def orszag_tang_timing(n, storage, steps, warmup):
     torch.cuda.synchronize()
     ms = start.elapsed_time(end) / steps
     red = s.reduce(allow_nonfinite=True)
+    diag = {}
+    if storage == "f64":
+        # one call of each diagnostic after an untimed one (FFT plans, workspaces); each syncs
+        ns = n // 2 + 1
+        calls = {"reduce": lambda: s.reduce(allow_nonfinite=True),
+                 "energy_spectra_u_B": lambda: (s.spectrum("u", ns), s.spectrum("B", ns)),
+                 "dissipation_spectra_u_B": lambda: (s.dissipation_spectrum("u", ns), s.dissipation_spectrum("B", ns)),
+                 "energy_transfer": lambda: s.energy_transfer(ns)}
+        for name, call in calls.items():
+            call()
+            t0 = time.perf_counter()
+            call()
+            diag[name] = round((time.perf_counter() - t0) * 1e3, 2)
     s.close()
     del s
     torch.cuda.empty_cache()
     mlups = n ** 3 / (ms * 1e-3) / 1e6
-    return {"storage": storage, "ms_per_step": ms, "mlups": mlups,
+    return {"storage": storage, "ms_per_step": ms, "mlups": mlups, "diagnostics_ms": diag or None,
             "achieved_GBps": bytes_per_node(storage, forced=False) * n ** 3 / (ms * 1e-3) / 1e9,
             "E_kin": float(red[0]), "E_mag": float(red[1]), "finite": int(red[8]) == 0,
             "vs_paper_3_gpus": mlups / PAPER_OT["value"], "vs_paper_per_gpu": mlups / PAPER_OT["per_gpu_MLUPS"]}

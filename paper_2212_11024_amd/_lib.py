@@ -50,6 +50,7 @@ _SIGNATURES = {
     "flame_spectrum": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
     "flame_dissipation_spectrum": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32,
                                                     ctypes.POINTER(ctypes.c_double)]),
+    "flame_energy_transfer": (ctypes.c_int32, [_P, ctypes.c_int32] + [ctypes.POINTER(ctypes.c_double)] * 3),
     "flame_get_populations": (ctypes.c_int32, [_P, _P, ctypes.c_int32]),
     "flame_set_populations": (ctypes.c_int32, [_P, _P, ctypes.c_int32]),
     "flame_gather": (ctypes.c_int32, [_P, _P, ctypes.c_int64, _P, ctypes.c_int32]),
@@ -149,6 +150,12 @@ def flame_dissipation_spectrum(ctx: int, field: int, nshells: int):
     out = (ctypes.c_double * nshells)()
     _check(load().flame_dissipation_spectrum(ctx, field, nshells, out), ctx)
     return list(out)
+
+
+def flame_energy_transfer(ctx: int, nshells: int):
+    out = [(ctypes.c_double * nshells)() for _ in range(3)]
+    _check(load().flame_energy_transfer(ctx, nshells, *out), ctx)
+    return [list(o) for o in out]
 
 
 def flame_get_populations(ctx: int, dst: int, deviations: int = 0) -> int:

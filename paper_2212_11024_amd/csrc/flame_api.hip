@@ -476,6 +476,100 @@ __global__ __launch_bounds__(kSpecThreads) void shell_bin_kernel(const hipfftDou
   for (int s = threadIdx.x; s < nshells; s += blockDim.x) partials[static_cast<size_t>(blockIdx.x) * nshells + s] = bins[s];
 }
 
+// ------------------------------------------------------------------ energy transfer
+// Derivative wavenumber 2 pi k / n of the DFT index idx (signed), 0 on the Nyquist index of an
+// even axis (that mode's derivative is not a real field).
+__device__ __forceinline__ double deriv_q(int idx, int n) {
+  return 2 * idx == n ? 0.0 : (2.0 * M_PI / n) * signed_freq(idx, n);
+}
+
+__device__ __forceinline__ void half_index(size_t k, int nx, int ny, int& kx, int& ky, int& kz) {
+  const int nxh = nx / 2 + 1;
+  kx = static_cast<int>(k % nxh);
+  const size_t r = k / nxh;
+  ky = static_cast<int>(r % ny);
+  kz = static_cast<int>(r / ny);
+}
+
+// out = i q_axis X / ncell on the half spectrum: the inverse real transform of out is the
+// derivative along axis of the field whose unnormalised forward transform is X.
+__global__ __launch_bounds__(256) void spectral_derivative_kernel(const hipfftDoubleComplex* X, int nx, int ny,
+                                                                  int nz, int axis, double inv_n,
+                                                                  hipfftDoubleComplex* out) {
+  const size_t total = static_cast<size_t>(nz) * ny * (nx / 2 + 1);
+  const size_t k = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= total) return;
+  int kx, ky, kz;
+  half_index(k, nx, ny, kx, ky, kz);
+  const double q = (axis == 0 ? deriv_q(kx, nx) : axis == 1 ? deriv_q(ky, ny) : deriv_q(kz, nz)) * inv_n;
+  const hipfftDoubleComplex x = X[k];
+  out[k] = make_hipDoubleComplex(-q * x.y, q * x.x);
+}
+
+// acc = (first ? 0 : acc) + a * b, node by node.
+__global__ __launch_bounds__(256) void product_accumulate_kernel(double* acc, const double* a, const double* b,
+                                                                 size_t n, int first) {
+  const size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  acc[i] = (first ? 0.0 : acc[i]) + a[i] * b[i];
+}
+
+// out = component comp of P x Q, with P and Q three consecutive arrays of n nodes.
+__global__ __launch_bounds__(256) void cross_component_kernel(const double* P, const double* Q, int comp, size_t n,
+                                                              double* out) {
+  const size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int c = (comp + 1) % 3, d = (comp + 2) % 3;
+  out[i] = P[c * n + i] * Q[d * n + i] - P[d * n + i] * Q[c * n + i];
+}
+
+// Per-block shell sums of one transfer summand over the half spectrum (entries with
+// 0 < kx < nx - kx stand for their mirror too, whose summand is equal). kind 0:
+// sign Re[conj(X) Y]; kind 1: -Re[i Y (conj(B_hat) x q)_comp] = -Re[conj(B_hat) . (i q x Y e_comp)]
+// summed over comp by the caller, with B_hat the three transforms in Bh. Adds into partials
+// unless first is set.
+__global__ __launch_bounds__(kSpecThreads) void transfer_bin_kernel(int kind, const hipfftDoubleComplex* X,
+                                                                    const hipfftDoubleComplex* Y,
+                                                                    const hipfftDoubleComplex* Bh, int comp,
+                                                                    double sign, int nx, int ny, int nz, int nshells,
+                                                                    double norm2, int first, double* partials) {
+  extern __shared__ double bins[];
+  for (int s = threadIdx.x; s < nshells; s += blockDim.x) bins[s] = 0.0;
+  __syncthreads();
+  const size_t nh = static_cast<size_t>(nz) * ny * (nx / 2 + 1);
+  const size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
+  for (size_t k = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; k < nh; k += stride) {
+    int kx, ky, kz;
+    half_index(k, nx, ny, kx, ky, kz);
+    const double fx = kx, fy = signed_freq(ky, ny), fz = signed_freq(kz, nz);
+    const int shell = static_cast<int>(floor(sqrt(fx * fx + fy * fy + fz * fz) + 0.5));
+    if (shell >= nshells) continue;
+    const hipfftDoubleComplex y = Y[k];
+    double v;
+    if (kind == 0) {
+      const hipfftDoubleComplex x = X[k];
+      v = sign * (x.x * y.x + x.y * y.y);
+    } else {
+      const double q[3] = {deriv_q(kx, nx), deriv_q(ky, ny), deriv_q(kz, nz)};
+      const int c = (comp + 1) % 3, d = (comp + 2) % 3;
+      const size_t plane = nh;
+      const hipfftDoubleComplex bc = Bh[c * plane + k], bd = Bh[d * plane + k];
+      // z = (conj(B_hat) x q)_comp = conj(B_c) q_d - conj(B_d) q_c
+      const double zr = bc.x * q[d] - bd.x * q[c];
+      const double zi = -bc.y * q[d] + bd.y * q[c];
+      // -Re[i y z] = Im[y z]
+      v = y.x * zi + y.y * zr;
+    }
+    const double mult = (kx == 0 || 2 * kx == nx) ? 1.0 : 2.0;
+    atomicAdd(&bins[shell], mult * v * norm2);
+  }
+  __syncthreads();
+  for (int s = threadIdx.x; s < nshells; s += blockDim.x) {
+    double& out = partials[static_cast<size_t>(blockIdx.x) * nshells + s];
+    out = first ? bins[s] : out + bins[s];
+  }
+}
+
 }  // namespace flame
 
 using namespace flame;
@@ -889,6 +983,129 @@ flame_status flame_dissipation_spectrum(flame_ctx* c, int32_t field, int32_t nsh
   return shell_spectrum(c, field, nshells, 1, d_k);
 }
 
+}  // extern "C"
+
+namespace {
+
+// Device buffers of one energy-transfer evaluation, released on every return.
+struct TransferScratch {
+  double* real = nullptr;              // U(3) B(3) J(3), a work field, the advection product
+  hipfftDoubleComplex* cplx = nullptr; // u_hat(3) B_hat(3), a work spectrum
+  double* partials = nullptr;          // 3 terms x blocks x nshells
+  ~TransferScratch() {
+    if (real) (void)hipFree(real);
+    if (cplx) (void)hipFree(cplx);
+    if (partials) (void)hipFree(partials);
+  }
+};
+
+flame_status energy_transfer(flame_ctx* c, int32_t nshells, double* t_adv, double* t_lor, double* t_ind) {
+  if (!c) return FLAME_E_INVAL;
+  if (nshells < 1 || nshells > kSpecShellsMax) return fail(c, FLAME_E_INVAL, "nshells out of range");
+  if (!t_adv || !t_lor || !t_ind) return fail(c, FLAME_E_INVAL, "an output array is NULL");
+  const int nx = c->p.nx, ny = c->p.ny, nz = c->p.nz;
+  const size_t n = c->n;
+  const size_t nh = static_cast<size_t>(nz) * ny * (nx / 2 + 1);
+  if (!c->plan_ok) {
+    if (hipfftPlan3d(&c->plan, nz, ny, nx, HIPFFT_D2Z) != HIPFFT_SUCCESS)
+      return fail(c, FLAME_E_HIP, "hipfftPlan3d failed");
+    c->plan_ok = true;
+    if (hipfftSetStream(c->plan, c->stream) != HIPFFT_SUCCESS) return fail(c, FLAME_E_HIP, "hipfftSetStream failed");
+  }
+  if (!c->plan_inv_ok) {
+    if (hipfftPlan3d(&c->plan_inv, nz, ny, nx, HIPFFT_Z2D) != HIPFFT_SUCCESS)
+      return fail(c, FLAME_E_HIP, "hipfftPlan3d (inverse) failed");
+    c->plan_inv_ok = true;
+    if (hipfftSetStream(c->plan_inv, c->stream) != HIPFFT_SUCCESS)
+      return fail(c, FLAME_E_HIP, "hipfftSetStream failed");
+  }
+  const int blocks = static_cast<int>(std::min<size_t>(1024, blocks_for(nh, kSpecThreads)));
+  TransferScratch w;
+  if (hipMalloc(&w.real, sizeof(double) * 11 * n) != hipSuccess ||
+      hipMalloc(&w.cplx, sizeof(hipfftDoubleComplex) * 7 * nh) != hipSuccess ||
+      hipMalloc(&w.partials, sizeof(double) * 3 * blocks * nshells) != hipSuccess)
+    return fail(c, FLAME_E_NOMEM, "energy transfer: device workspace");
+  double* U = w.real;
+  double* B = w.real + 3 * n;
+  double* J = w.real + 6 * n;
+  double* work = w.real + 9 * n;
+  double* adv = w.real + 10 * n;
+  hipfftDoubleComplex* Uh = w.cplx;
+  hipfftDoubleComplex* Bh = w.cplx + 3 * nh;
+  hipfftDoubleComplex* spec = w.cplx + 6 * nh;
+  const unsigned gn = blocks_for(n, 256), gh = blocks_for(nh, 256);
+  hipError_t e = by_storage(c, [&](auto tag) {
+    using S = decltype(tag);
+    hipLaunchKernelGGL(moments_kernel<S>, dim3(gn), dim3(256), 0, c->stream, make_aux<S>(c), nullptr, U, B, J,
+                       nullptr);
+    return hipGetLastError();
+  });
+  if (e != hipSuccess) return fail(c, FLAME_E_HIP, std::string("energy transfer fields: ") + hipGetErrorString(e));
+  // forward transforms run on the work copy: the transform may overwrite its input
+  auto forward = [&](const double* src, hipfftDoubleComplex* dst) -> bool {
+    if (src != work && hipMemcpyAsync(work, src, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+      return false;
+    return hipfftExecD2Z(c->plan, work, dst) == HIPFFT_SUCCESS;
+  };
+  const double norm2 = 1.0 / (static_cast<double>(n) * static_cast<double>(n));
+  auto bin = [&](int kind, int term, const hipfftDoubleComplex* X, int comp, double sign, bool first) {
+    hipLaunchKernelGGL(transfer_bin_kernel, dim3(blocks), dim3(kSpecThreads), sizeof(double) * nshells, c->stream,
+                       kind, X, spec, Bh, comp, sign, nx, ny, nz, nshells, norm2, first ? 1 : 0,
+                       w.partials + static_cast<size_t>(term) * blocks * nshells);
+    return hipGetLastError() == hipSuccess;
+  };
+  bool ok = true;
+  for (int b = 0; b < 3 && ok; ++b) ok = forward(U + b * n, Uh + b * nh) && forward(B + b * n, Bh + b * nh);
+  for (int b = 0; b < 3 && ok; ++b) {
+    // (U . grad) U_b, with grad U_b from the inverse transform of i q_a u_hat_b
+    for (int a = 0; a < 3 && ok; ++a) {
+      hipLaunchKernelGGL(spectral_derivative_kernel, dim3(gh), dim3(256), 0, c->stream, Uh + b * nh, nx, ny, nz, a,
+                         1.0 / static_cast<double>(n), spec);
+      ok = hipGetLastError() == hipSuccess && hipfftExecZ2D(c->plan_inv, spec, work) == HIPFFT_SUCCESS;
+      if (ok) {
+        hipLaunchKernelGGL(product_accumulate_kernel, dim3(gn), dim3(256), 0, c->stream, adv, U + a * n, work, n,
+                           a == 0 ? 1 : 0);
+        ok = hipGetLastError() == hipSuccess;
+      }
+    }
+    ok = ok && forward(adv, spec) && bin(0, 0, Uh + b * nh, b, 1.0, b == 0);
+    // Lorentz force (J x B)_b
+    if (ok) {
+      hipLaunchKernelGGL(cross_component_kernel, dim3(gn), dim3(256), 0, c->stream, J, B, b, n, work);
+      ok = hipGetLastError() == hipSuccess && forward(work, spec) && bin(0, 1, Uh + b * nh, b, -1.0, b == 0);
+    }
+    // induction: (U x B)_b, binned against conj(B_hat) x q
+    if (ok) {
+      hipLaunchKernelGGL(cross_component_kernel, dim3(gn), dim3(256), 0, c->stream, U, B, b, n, work);
+      ok = hipGetLastError() == hipSuccess && forward(work, spec) && bin(1, 2, nullptr, b, 1.0, b == 0);
+    }
+  }
+  std::vector<double> host(static_cast<size_t>(3) * blocks * nshells);
+  if (ok) ok = hipMemcpyAsync(host.data(), w.partials, sizeof(double) * host.size(), hipMemcpyDeviceToHost,
+                              c->stream) == hipSuccess;
+  if (ok) ok = hipStreamSynchronize(c->stream) == hipSuccess;
+  if (!ok) {
+    const hipError_t last = hipGetLastError();
+    return fail(c, FLAME_E_HIP, std::string("energy transfer: a transform, copy or kernel launch failed (") +
+                                    hipGetErrorString(last) + ")");
+  }
+  double* outs[3] = {t_adv, t_lor, t_ind};
+  for (int t = 0; t < 3; ++t) {
+    for (int s = 0; s < nshells; ++s) outs[t][s] = 0.0;
+    for (int blk = 0; blk < blocks; ++blk)
+      for (int s = 0; s < nshells; ++s) outs[t][s] += host[(static_cast<size_t>(t) * blocks + blk) * nshells + s];
+  }
+  return FLAME_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+flame_status flame_energy_transfer(flame_ctx* c, int32_t nshells, double* t_adv, double* t_lor, double* t_ind) {
+  return energy_transfer(c, nshells, t_adv, t_lor, t_ind);
+}
+
 flame_status flame_get_populations(flame_ctx* c, double* dst, int32_t deviations) {
   if (!c || !dst) return c ? fail(c, FLAME_E_INVAL, "dst is NULL") : FLAME_E_INVAL;
   hipError_t e = by_storage(c, [&](auto tag) {
@@ -973,6 +1190,7 @@ void flame_destroy(flame_ctx* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
   if (c->plan_ok) hipfftDestroy(c->plan);
+  if (c->plan_inv_ok) hipfftDestroy(c->plan_inv);
   if (c->red_partials) (void)hipFree(c->red_partials);
   if (c->spec_real) (void)hipFree(c->spec_real);
   if (c->spec_cplx) (void)hipFree(c->spec_cplx);

@@ -34,6 +34,8 @@ struct flame_ctx {
   int spec_nshells = 0;
   hipfftHandle plan{};
   bool plan_ok = false;
+  hipfftHandle plan_inv{};   // complex-to-real inverse, for spectral derivatives
+  bool plan_inv_ok = false;
 };
 
 namespace flame {

@@ -105,6 +105,11 @@ class Solver:
         return torch.tensor(L.flame_dissipation_spectrum(self.ctx, {"u": 0, "B": 1}.get(field, field), nshells),
                             dtype=torch.float64)
 
+    def energy_transfer(self, nshells):
+        """(T_adv, T_lor, T_ind) per shell, float64 (3, nshells): the summands of the flux
+        S_MHD(k) = sum_{s < k} (T_adv + T_lor + T_ind) of the scale-by-scale energy budget."""
+        return torch.tensor(L.flame_energy_transfer(self.ctx, nshells), dtype=torch.float64)
+
     # -- canonical state
     def get_populations(self, deviations=False):
         """(f (27, nz, ny, nx), g (7, 3, nz, ny, nx)) float64 on device: full values, or the
