@@ -36,3 +36,29 @@ def wave(nz: int, t: float, amp: float, b0: float, nu: float, alpha_h: float, br
     b = be * u
     b[2] += b0
     return u, b
+
+
+def emhd_frequency(alpha_h: float, k: float, b0: float) -> float:
+    """Whistler frequency of the electron-MHD induction equation (Sec. 6: the magnetic
+    equilibrium without the bulk velocity), w = alpha_H b0 k^2.
+
+    With V = -alpha_H J the magnetic scheme solves dB/dt = -alpha_H curl(J x B) + eta lap B. For
+    B = b0 z_hat + b(z, t), b perpendicular to z: J = curl b lies in the plane, J x b is along z
+    and depends on z only (its curl vanishes), and J x (b0 z_hat) = b0 d_z b, so
+    d_t b_x = alpha_H b0 d_z^2 b_y + eta d_z^2 b_x, d_t b_y = -alpha_H b0 d_z^2 b_x + eta d_z^2 b_y.
+    b = a exp(-eta k^2 t) (sin(k z - w t), cos(k z - w t), 0) solves this exactly for
+    w = alpha_H b0 k^2, whatever the fluid does."""
+    return alpha_h * b0 * k * k
+
+
+def emhd_wave(nz: int, t: float, amp: float, b0: float, eta: float, alpha_h: float, mode: int = 1):
+    """Exact electron-MHD field B(z, t) (includes b0 along z) on z = 0..nz-1: (3, nz)."""
+    k = 2.0 * math.pi * mode / nz
+    w = emhd_frequency(alpha_h, k, b0)
+    z = torch.arange(nz, dtype=torch.float64)
+    ph = k * z - w * t
+    damp = amp * math.exp(-eta * k * k * t)
+    b = torch.stack([damp * torch.sin(ph), damp * torch.cos(ph), torch.zeros_like(ph)])
+    b[2] += b0
+    return b
+

@@ -130,3 +130,18 @@ def collide_closed(f, rho, U, B, omega, F=None):
         for a, p in enumerate([(1, 0, 0), (0, 1, 0), (0, 0, 1)]):
             out = out + 0.5 * F[a] * unit_central_moment_dist(U, p)
     return out
+
+
+def collide_bgk_closed(f, rho, U, B, omega, F=None):
+    """Closed form of the BGK limit S = omega I of collide_T (Sec. 3.1.2: the BGK collision is
+    the central-moment one with every rate equal to omega): f0 + (1 - omega)(f - f0). With a
+    force the first central moments are set to F/2 as in the central-moment scheme; before the
+    collision those of f - f0 are -F/2 (U carries F/2), so the force adds (1 - omega/2) F_a times
+    the distribution with a unit first central moment along a."""
+    f0 = f_mhd_eq(rho, U, B)
+    out = f0 + (1.0 - omega) * (f - f0)
+    if F is not None:
+        for a, p in enumerate([(1, 0, 0), (0, 1, 0), (0, 0, 1)]):
+            out = out + (1.0 - 0.5 * omega) * F[a] * unit_central_moment_dist(U, p)
+    return out
+

@@ -6,8 +6,8 @@ the rest state that can be 1e-3..1e-4 of that size, so its own rounding is ampli
 the quantities being compared, and the flow amplifies it further over many steps. This module
 runs the same definition with ~2000x smaller rounding, which (a) measures the FP64 oracle's
 floor and (b) serves as the reference for FP64 parity. It follows the paper passages named in
-oracle.scheme; the fluid collision uses the exact closed form of the central-moment collision
-(pinned equal to the T-matrix definition in tests/test_oracle_collision_current.py), the
+oracle.scheme; the fluid collision uses the exact closed form of the central-moment collision or
+of its BGK limit (pinned equal to the T-matrix definition in tests/test_oracle_collision_current.py), the
 equilibrium the D1Q3 product form (pinned equal to App. A's Hermite expansion), and J the
 3x3 system of Sec. 3.2 solved by Cramer's rule (numpy's solver has no extended precision).
 """
@@ -45,6 +45,10 @@ class Params:
         self.omega_b = LD(1) / (self.eta / C2 + LD(0.5))
         self.F = _ld(p.force_u)
         self.S = _ld(p.force_b)
+        self.collision = p.collision
+        self.magnetic = p.magnetic
+        if self.collision not in ("central", "bgk") or self.magnetic not in ("hall", "emhd"):
+            raise ValueError((self.collision, self.magnetic))
 
 
 def _phi(c, u):
@@ -130,20 +134,27 @@ def step(f, g, p: Params, nsteps=1):
         if p.S is not None:
             B = B + LD(0.5) * p.S
         Lam = np.einsum("ia,ib...->ab...", XI, g)
-        J = _current(p, U, B, Lam)
+        Um = np.zeros_like(U) if p.magnetic == "emhd" else U
+        J = _current(p, Um, B, Lam)
         f0 = f_mhd_eq(rho, U, B)
-        d = f - f0
-        cb = C.T.reshape(3, 27, *([1] * U[0].ndim)) - U[:, None]
-        K = np.einsum("ai...,bi...,i...->ab...", cb, cb, d)
-        tr = (K[0, 0] + K[1, 1] + K[2, 2]) / 3
-        fs = f0.copy()
-        for (a, b), pp in _PAIRS.items():
-            Pab = K[a, b] - (tr if a == b else 0)
-            fs += (1 - p.omega) * Pab * _unit(U, pp)
-        if p.F is not None:
-            for a, pp in enumerate(_FIRST):
-                fs += LD(0.5) * p.F[a] * _unit(U, pp)
-        V = U - p.d_i * J
+        if p.collision == "bgk":
+            fs = f0 + (1 - p.omega) * (f - f0)
+            if p.F is not None:
+                for a, pp in enumerate(_FIRST):
+                    fs += (1 - p.omega / 2) * p.F[a] * _unit(U, pp)
+        else:
+            d = f - f0
+            cb = C.T.reshape(3, 27, *([1] * U[0].ndim)) - U[:, None]
+            K = np.einsum("ai...,bi...,i...->ab...", cb, cb, d)
+            tr = (K[0, 0] + K[1, 1] + K[2, 2]) / 3
+            fs = f0.copy()
+            for (a, b), pp in _PAIRS.items():
+                Pab = K[a, b] - (tr if a == b else 0)
+                fs += (1 - p.omega) * Pab * _unit(U, pp)
+            if p.F is not None:
+                for a, pp in enumerate(_FIRST):
+                    fs += LD(0.5) * p.F[a] * _unit(U, pp)
+        V = Um - p.d_i * J
         xv = np.einsum("ib,b...->i...", XI, V)
         xb = np.einsum("ib,b...->i...", XI, B)
         geq = WM.reshape(7, 1, *([1] * U[0].ndim)) * (B[None] + (xv[:, None] * B[None] - xb[:, None] * V[None]) / C2)
@@ -176,7 +187,7 @@ def init_state(p: Params, u, b, grad_u=None, grad_b=None, noneq=True):
             f = f - LD(0.5) * p.F[a] * _unit(u, pp)
     J = np.zeros_like(u) if gb is None else np.stack(
         [gb[1, 2] - gb[2, 1], gb[2, 0] - gb[0, 2], gb[0, 1] - gb[1, 0]])
-    V = u - p.d_i * J
+    V = (np.zeros_like(u) if p.magnetic == "emhd" else u) - p.d_i * J
     xv = np.einsum("ib,b...->i...", XI, V)
     xb = np.einsum("ib,b...->i...", XI, B)
     wm = WM.reshape(7, 1, 1, 1, 1)

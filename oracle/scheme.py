@@ -18,6 +18,10 @@ non-equilibrium part whose deviatoric second central moment is
 -(rho c_s^2 / w)(grad u + grad u^T - 2/3 div u I); g = g^Hall(0)(u, B, curl B) plus
 -(1 / w_B) W_i xi_ia d_a B_b, so that Lambda - Lambda0 = -(C^2 / w_B) grad B at t = 0.
 With forcing, -F/2 and -S/2 are added so that the node moments return exactly u and B.
+
+Variants (Params.collision, Params.magnetic): the BGK fluid collision, which is the same step
+with S = omega I (Sec. 3.1.2); and electron MHD (Sec. 6), whose magnetic equilibrium, the J
+system built on it and the initial magnetic state take the bulk velocity as zero.
 """
 
 from __future__ import annotations
@@ -46,6 +50,12 @@ class Params:
     route: str = "T"                       # fluid collision: "T" (definition) or "closed"
     force_u: Optional[torch.Tensor] = None  # (3, nz, ny, nx) fluid body force F
     force_b: Optional[torch.Tensor] = None  # (3, nz, ny, nx) magnetic source S
+    # fluid collision: "central" (the paper's central-moment MRT, eq. collision_matrix) or "bgk"
+    # (S = omega I, the standard BGK operator of Sec. 3.1.1)
+    collision: str = "central"
+    # magnetic equilibrium: "hall" (eq. gHall_eq, V = U - alpha_H J) or "emhd" (electron MHD,
+    # Sec. 6: the bulk velocity neglected against the Hall current, V = -alpha_H J)
+    magnetic: str = "hall"
 
     @property
     def omega(self):
@@ -87,7 +97,18 @@ def moments(st: State, p: Params):
     return rho, U, B, Lam
 
 
+def magnetic_velocity(p: Params, U):
+    """The bulk velocity as the magnetic equilibrium and the J system see it: U, or 0 for
+    electron MHD."""
+    if p.magnetic == "hall":
+        return U
+    if p.magnetic == "emhd":
+        return torch.zeros_like(U)
+    raise ValueError(p.magnetic)
+
+
 def current(p: Params, U, B, Lam):
+    """J of the current route; U is the magnetic_velocity."""
     if p.jmode == "moment":
         sh = B.shape[1:]
         n = B[0].numel()
@@ -101,17 +122,21 @@ def current(p: Params, U, B, Lam):
 def collide(st: State, p: Params) -> State:
     """Post-collision populations at every node."""
     rho, U, B, Lam = moments(st, p)
-    J = current(p, U, B, Lam)
+    Um = magnetic_velocity(p, U)
+    J = current(p, Um, B, Lam)
     n = p.ncell
     F = None if p.force_u is None else p.force_u.reshape(3, n)
     args = (st.f.reshape(27, n), rho.reshape(n), U.reshape(3, n), B.reshape(3, n), p.omega)
+    if p.collision not in ("central", "bgk"):
+        raise ValueError(p.collision)
     if p.route == "T":
-        fs = collision.collide_T(*args, F=F)
+        rates = torch.full((27,), p.omega, dtype=DT) if p.collision == "bgk" else None
+        fs = collision.collide_T(*args, F=F, rates=rates)
     elif p.route == "closed":
-        fs = collision.collide_closed(*args, F=F)
+        fs = (collision.collide_bgk_closed if p.collision == "bgk" else collision.collide_closed)(*args, F=F)
     else:
         raise ValueError(p.route)
-    geq = g_eq_hall(U, B, J, p.d_i)
+    geq = g_eq_hall(Um, B, J, p.d_i)
     gs = st.g - p.omega_b * (st.g - geq)
     if p.force_b is not None:
         gs = gs + (1.0 - 0.5 * p.omega_b) * WM.view(7, 1, 1, 1, 1) * p.force_b.unsqueeze(0)
@@ -160,7 +185,7 @@ def init_state(p: Params, u, b, grad_u=None, grad_b=None, noneq=True) -> State:
     rho = torch.ones(sh, dtype=DT)
     f = f_mhd_eq(rho, u, B)
     J = torch.zeros_like(u) if grad_b is None else curl_from_gradient(grad_b)
-    g = g_eq_hall(u, B, J, p.d_i)
+    g = g_eq_hall(magnetic_velocity(p, u), B, J, p.d_i)
     kneq = torch.zeros((n, 27), dtype=DT)
     if noneq and grad_u is not None:
         s = grad_u + grad_u.transpose(0, 1)
@@ -189,7 +214,7 @@ def init_state(p: Params, u, b, grad_u=None, grad_b=None, noneq=True) -> State:
 def fields(st: State, p: Params):
     """Node fields of the current state: rho, u, B, J, div B (moment estimate)."""
     rho, U, B, Lam = moments(st, p)
-    J = current(p, U, B, Lam)
+    J = current(p, magnetic_velocity(p, U), B, Lam)
     return rho, U, B, J, divergence_moment(Lam, p.omega_b)
 
 

@@ -28,6 +28,8 @@ class Case:
     seed: int = 0
     kmax: int = 2
     ic: str = "shell"      # "shell": seeded shell fields; "orszag_tang": u amplitude rms, B amplitude 0.8 rms
+    collision: str = "central"   # fluid collision: "central" or "bgk"
+    magnetic: str = "hall"       # magnetic equilibrium: "hall" or "emhd"
 
     @property
     def shape(self):
@@ -55,7 +57,7 @@ def inputs(case: Case, device="cpu"):
 
 def oracle_params(case: Case, fu=None, fb=None, route="closed"):
     return scheme.Params(case.nx, case.ny, case.nz, case.nu, case.eta, case.d_i, case.b0, case.jmode, route,
-                         fu, fb)
+                         fu, fb, collision=case.collision, magnetic=case.magnetic)
 
 
 def oracle_run(case: Case, steps: int, route="closed", noneq=True, ftype=torch.float64):

@@ -58,6 +58,24 @@ def test_bgk_limit():
     assert (fs - (f - omega * (f - f_mhd_eq(rho, U, B)))).abs().max() < 1e-15
 
 
+def test_bgk_closed_form_equals_T_route():
+    """The BGK variant's closed form against the definition with every rate equal to omega, with
+    and without a force (first central moments set to F/2); the force adds F to the momentum."""
+    f, rho, U0, B = _random_populations(300)
+    F = 1e-3 * torch.randn(3, 300, dtype=torch.float64)
+    mom = torch.einsum("in,ia->an", f, C)
+    U = (mom + 0.5 * F) / rho
+    for omega in (0.6, 1.0, 1.9):
+        rates = torch.full((27,), omega, dtype=torch.float64)
+        for FF, UU in ((None, U0), (F, U)):
+            a = col.collide_T(f, rho, UU, B, omega, F=FF, rates=rates)
+            b = col.collide_bgk_closed(f, rho, UU, B, omega, F=FF)
+            assert (a - b).abs().max() < 1e-15
+        fs = col.collide_bgk_closed(f, rho, U, B, omega, F=F)
+        assert torch.allclose(torch.einsum("in,ia->an", fs, C), mom + F, atol=1e-15, rtol=0)
+        assert torch.allclose(fs.sum(0), rho, atol=1e-14, rtol=0)
+
+
 def test_post_collision_central_moments():
     # second-order deviatoric non-equilibrium scaled by (1 - omega); trace and every
     # higher moment (per-axis degree <= 2) at equilibrium

@@ -19,7 +19,10 @@ def _rel(st, p, ref):
 
 
 @pytest.mark.parametrize("case", [Case(8, 7, 6, jmode="moment", seed=11), Case(8, 7, 6, jmode="stencil", seed=11),
-                                  Case(6, 6, 6, jmode="stencil", forced=True, seed=5, d_i=4.0)])
+                                  Case(6, 6, 6, jmode="stencil", forced=True, seed=5, d_i=4.0),
+                                  Case(7, 6, 5, jmode="moment", forced=True, seed=6, collision="bgk"),
+                                  Case(7, 6, 5, jmode="moment", forced=True, seed=8, magnetic="emhd"),
+                                  Case(7, 6, 5, jmode="stencil", seed=10, collision="bgk", magnetic="emhd")])
 def test_extended_agrees_with_fp64_oracle(case):
     for steps, tol in ((0, 1e-14), (3, 1e-13)):
         p, st = oracle_run(case, steps, route="T")

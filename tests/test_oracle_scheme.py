@@ -17,8 +17,8 @@ TOL_WAVE = {"stencil": 0.01, "moment": 0.05}
 
 
 def _wave_run(N, steps, amp, b0, d_i, nu=0.01, branch=+1, jmode="stencil", nx=1, ny=1,
-              route="closed"):
-    p = scheme.Params(nx, ny, N, nu, nu, d_i, (0.0, 0.0, b0), jmode, route)
+              route="closed", collision="central"):
+    p = scheme.Params(nx, ny, N, nu, nu, d_i, (0.0, 0.0, b0), jmode, route, collision=collision)
     be = analytic.beta(d_i, 2 * math.pi / N, branch)
     uf = synthetic.wave_field(amp)
     u, gu = synthetic.evaluate(uf, (nx, ny, N))
@@ -59,6 +59,41 @@ def test_second_order_convergence_diffusive_scaling(jmode):
         errs.append(max(eu, eb))
     slope = np.polyfit(np.log(Ns), np.log(errs), 1)[0]
     assert slope < -1.8, (errs, slope)
+
+
+@pytest.mark.parametrize("jmode", ["stencil", "moment"])
+def test_exact_hall_wave_bgk_fluid(jmode):
+    # the BGK fluid variant (S = omega I) carries the same Navier-Stokes viscosity: the same
+    # exact wave and bound as the central-moment collision
+    eu, eb = _wave_error(32, 200, 1e-3, 0.1, 2.0, jmode=jmode, collision="bgk")
+    assert eu < TOL_WAVE[jmode] and eb < TOL_WAVE[jmode], (eu, eb)
+
+
+def _emhd_error(N, steps, amp, b0, d_i, jmode, eta=0.01):
+    """Electron-MHD run of the exact whistler (fluid at rest at t = 0; the magnetic scheme does
+    not see the fluid): relative error of B - b0 after the given steps."""
+    p = scheme.Params(1, 1, N, eta, eta, d_i, (0.0, 0.0, b0), jmode, "closed", magnetic="emhd")
+    b, gb = synthetic.evaluate(synthetic.wave_field(amp), (1, 1, N))
+    z = torch.zeros_like(b)
+    st = scheme.step(scheme.init_state(p, z, b, torch.zeros_like(gb), gb), p, steps)
+    _, _, B, _, _ = scheme.fields(st, p)
+    be = analytic.emhd_wave(N, steps, amp, b0, eta, d_i)
+    bf = be.clone()
+    bf[2] -= b0
+    return float(torch.linalg.norm(B[:, :, 0, 0] - be) / torch.linalg.norm(bf))
+
+
+@pytest.mark.parametrize("jmode", ["stencil", "moment"])
+def test_exact_emhd_whistler_second_order(jmode):
+    # electron MHD (Sec. 6): the whistler w = alpha_H b0 k^2 of oracle.analytic, within the wave
+    # bound at 32 nodes per wavelength and second order under diffusive scaling
+    Ns = [16, 32, 64]
+    errs = []
+    for N in Ns:
+        s = N / 32
+        errs.append(_emhd_error(N, int(round(200 * s * s)), 1e-3 / s, 0.1 / s, 2.0 * s, jmode))
+    slope = np.polyfit(np.log(Ns), np.log(errs), 1)[0]
+    assert errs[1] < TOL_WAVE[jmode] and slope < -1.8, (errs, slope)
 
 
 def test_translation_invariance():
