@@ -14,10 +14,12 @@ Prints one JSON line. The headline is the FP32 step with J from the magnetic mom
 paper's route), which stays stable on this workload. The variants time the same workload with
 the curl-stencil J (its kernel stages b tiles in LDS; the explicit stencil makes the Hall term
 linearly unstable at these parameters, so its state turns non-finite within about a hundred
-steps, which each variant reports), with d_i = 0 for the stencil kernel, and with FP64 and FP16
-storage. Also reported: the roofline of the headline kernel (algorithmic bytes per launch over
-the event-timed average launch), the reverse-mode cost on the adjoint workload, and the CPU
-oracle timed on a bounded sample on the host cores.
+steps, which each variant reports), with d_i = 0 for the stencil kernel, with FP64 and FP16
+storage, and with the model variants (BGK fluid collision; electron MHD). Also reported: the
+roofline of the headline kernel (algorithmic bytes per launch over the event-timed average
+launch), the paper's own Orszag-Tang workload at 512^3 with the cost of the diagnostics, the
+reverse-mode cost on the adjoint workload, and the CPU oracle timed on a bounded sample on the
+host cores.
 """
 
 from __future__ import annotations
@@ -37,7 +39,7 @@ HBM_PEAK_GBPS = 8000.0        # MI355X HBM3E peak
 # HBM traffic of the headline kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE passes, calibrated on
 # a plain copy (see the traffic summary named below). Valid only for the kernel source it was
 # measured on: reported as null once the fingerprint of the kernel sources changes.
-TRAFFIC_RECORD = {"fingerprint": "d44a3f46f0be8647", "GB_per_launch": 55.32,
+TRAFFIC_RECORD = {"fingerprint": "845b728891c4796b", "GB_per_launch": 55.3,
                   "profile": "profiles/traffic_step_f32_moment_512.md"}
 
 
@@ -66,12 +68,14 @@ def workload_fields(n, device):
 PHYS = dict(nu=0.001, eta=0.001, d_i=4.0, b0=(0.0, 0.0, 0.0))
 
 
-def make_solver(n, storage="f32", jmode="moment", layout="aa", device="cuda", fields=None, d_i=None):
+def make_solver(n, storage="f32", jmode="moment", layout="aa", device="cuda", fields=None, d_i=None,
+                collision="central", magnetic="hall", placement_trials=1):
     import torch
     from paper_2212_11024_amd.solver import Solver
     u, gu, b, gb, fu, fb = fields if fields is not None else workload_fields(n, device)
     s = Solver(n, n, n, PHYS["nu"], PHYS["eta"], PHYS["d_i"] if d_i is None else d_i, PHYS["b0"], storage, jmode,
-               layout, u, b, gu, gb, fu, fb, device=device)
+               layout, u, b, gu, gb, fu, fb, device=device, collision=collision, magnetic=magnetic,
+               placement_trials=placement_trials)
     torch.cuda.synchronize()
     return s
 
@@ -84,9 +88,12 @@ def bytes_per_node(storage, forced=True):
     return 2 * 48 * vb + (6 * fb if forced else 0)
 
 
-def time_variant(n, storage, jmode, d_i, steps, warmup, fields):
+def time_variant(n, storage, jmode, d_i, steps, warmup, fields, collision="central", magnetic="hall",
+                 placement_trials=1):
     import torch
-    s = make_solver(n, storage, jmode, "aa", fields=fields, d_i=d_i)
+    s = make_solver(n, storage, jmode, "aa", fields=fields, d_i=d_i, collision=collision, magnetic=magnetic,
+                    placement_trials=placement_trials)
+    placement = s.placement_ms
     s.step(warmup)
     torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
@@ -107,12 +114,14 @@ def time_variant(n, storage, jmode, d_i, steps, warmup, fields):
     nodes = n ** 3
     bpn = bytes_per_node(storage)
     return {
-        "storage": storage, "jmode": jmode, "d_i": d_i, "ms_per_step": ms, "wall_s": wall,
+        "storage": storage, "jmode": jmode, "d_i": d_i, "collision": collision, "magnetic": magnetic,
+        "ms_per_step": ms, "wall_s": wall,
         "mlups": nodes / (ms * 1e-3) / 1e6,
         "bytes_per_node": bpn,
         "achieved_GBps": bpn * nodes / (ms * 1e-3) / 1e9,
         "E_kin": float(red[0]), "E_mag": float(red[1]), "nonfinite_nodes": int(red[8]),
         "finite": int(red[8]) == 0,
+        "placement_trials_ms": [round(t, 3) for t in placement] if placement else None,
         "_spectra": spectra,
     }
 
@@ -157,7 +166,7 @@ def orszag_tang_params(n, ma=OT_RUN_I["ma"], b_ratio=OT_RUN_I["b_ratio"], eps_h=
     return {"u_amp": u0, "b_amp": b_ratio * u0, "nu": nu, "eta": nu, "d_i": eps_h * n}
 
 
-def orszag_tang_timing(n, storage, steps, warmup):
+def orszag_tang_timing(n, storage, steps, warmup, placement_trials=1):
     """Event-timed steps of the Orszag-Tang workload (moment J, AA, unforced) on an n^3 grid."""
     import torch
     import synthetic
@@ -166,8 +175,10 @@ def orszag_tang_timing(n, storage, steps, warmup):
     fu, fb = synthetic.orszag_tang(q["u_amp"], q["b_amp"])
     u, gu = synthetic.evaluate(fu, (n, n, n), "cuda")
     b, gb = synthetic.evaluate(fb, (n, n, n), "cuda")
-    s = Solver(n, n, n, q["nu"], q["eta"], q["d_i"], (0.0, 0.0, 0.0), storage, "moment", "aa", u, b, gu, gb)
+    s = Solver(n, n, n, q["nu"], q["eta"], q["d_i"], (0.0, 0.0, 0.0), storage, "moment", "aa", u, b, gu, gb,
+               placement_trials=placement_trials)
     del u, b, gu, gb
+    placement = s.placement_ms
     s.step(warmup)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
@@ -197,6 +208,7 @@ def orszag_tang_timing(n, storage, steps, warmup):
     torch.cuda.empty_cache()
     mlups = n ** 3 / (ms * 1e-3) / 1e6
     return {"storage": storage, "ms_per_step": ms, "mlups": mlups, "diagnostics_ms": diag or None,
+            "placement_trials_ms": [round(t, 3) for t in placement] if placement else None,
             "achieved_GBps": bytes_per_node(storage, forced=False) * n ** 3 / (ms * 1e-3) / 1e9,
             "E_kin": float(red[0]), "E_mag": float(red[1]), "finite": int(red[8]) == 0,
             "vs_paper_3_gpus": mlups / PAPER_OT["value"], "vs_paper_per_gpu": mlups / PAPER_OT["per_gpu_MLUPS"]}
@@ -361,6 +373,9 @@ def main(argv=None):
     ap.add_argument("--no-copy-probe", action="store_true",
                     help="skip the plain 4 GiB device copy (bandwidth reference and counter calibration)")
     ap.add_argument("--copy-probe", action="store_true", help="time the copy also with --variants headline/stencil")
+    ap.add_argument("--placement-trials", type=int, default=8,
+                    help="candidate population buffers per timed run; the fastest over a 3-step probe is kept "
+                         "(the step's speed depends on the physical memory behind the buffer)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU slab "
@@ -378,8 +393,8 @@ def main(argv=None):
         print(json.dumps([adjoint_timing(128, "f32", jm, recompute=rc) for jm, rc in adjoint_cases]), flush=True)
         return 0
     if args.variants == "orszag-tang":
-        print(json.dumps([orszag_tang_timing(args.size, st, args.steps, args.warmup) for st in ("f64", "f32")]),
-              flush=True)
+        print(json.dumps([orszag_tang_timing(args.size, st, args.steps, args.warmup, args.placement_trials)
+                          for st in ("f64", "f32")]), flush=True)
         return 0
     n = args.size
     copy = copy_probe() if (args.copy_probe or (args.variants == "all" and not args.no_copy_probe)) else None
@@ -389,21 +404,25 @@ def main(argv=None):
     variants = [("f32", "stencil", d_i)] if args.variants == "stencil" else [("f32", "moment", d_i)]
     if args.variants == "all":
         variants += [("f32", "stencil", d_i), ("f32", "stencil", 0.0), ("f64", "moment", d_i),
-                     ("f64", "stencil", d_i), ("f16", "moment", d_i), ("f16", "stencil", d_i)]
+                     ("f64", "stencil", d_i), ("f16", "moment", d_i), ("f16", "stencil", d_i),
+                     # model variants of the same workload: BGK fluid collision, electron MHD
+                     ("f32", "moment", d_i, "bgk", "hall"), ("f32", "moment", d_i, "central", "emhd")]
     results = []
-    for storage, jmode, di in variants:
-        print(f"[bench] {n}^3 {storage} {jmode} d_i={di}: {args.warmup} warm-up + {args.steps} timed steps",
-              file=sys.stderr, flush=True)
-        r = time_variant(n, storage, jmode, di, args.steps, args.warmup, fields)
+    for storage, jmode, di, *model in variants:
+        coll, mag = model or ("central", "hall")
+        print(f"[bench] {n}^3 {storage} {jmode} d_i={di} {coll} {mag}: {args.warmup} warm-up + {args.steps} "
+              "timed steps", file=sys.stderr, flush=True)
+        r = time_variant(n, storage, jmode, di, args.steps, args.warmup, fields, coll, mag, args.placement_trials)
         print(f"[bench]   {r['ms_per_step']:.3f} ms/step, {r['mlups']:.0f} MLUPS, {r['achieved_GBps']:.0f} GB/s, "
               f"non-finite nodes {r['nonfinite_nodes']}", file=sys.stderr, flush=True)
         results.append(r)
     del fields
     torch.cuda.empty_cache()
-    ref = {(r["jmode"], r["d_i"]): r["_spectra"] for r in results if r["storage"] == "f64"}
+    ref = {(r["jmode"], r["d_i"], r["collision"], r["magnetic"]): r["_spectra"] for r in results
+           if r["storage"] == "f64"}
     for r in results:
         sp = r.pop("_spectra")
-        key = (r["jmode"], r["d_i"])
+        key = (r["jmode"], r["d_i"], r["collision"], r["magnetic"])
         if r["storage"] != "f64" and key in ref:
             err = spectral_error(sp, ref[key])
             r["spectral_error_vs_f64"] = {f: {k: (round(v, 8) if math.isfinite(v) else None) for k, v in e.items()}
@@ -413,7 +432,7 @@ def main(argv=None):
         for st in ("f64", "f32"):
             print(f"[bench] Orszag-Tang {n}^3 {st} (paper's workload, Tab. 2 run I parameters)", file=sys.stderr,
                   flush=True)
-            ot.append(orszag_tang_timing(n, st, args.steps, args.warmup))
+            ot.append(orszag_tang_timing(n, st, args.steps, args.warmup, args.placement_trials))
             print(f"[bench]   {ot[-1]['ms_per_step']:.3f} ms/step, {ot[-1]['mlups']:.0f} MLUPS", file=sys.stderr,
                   flush=True)
     adj = []
@@ -446,7 +465,9 @@ def main(argv=None):
         "config": {"workload": WORKLOAD if n == 512 else WORKLOAD.replace("512^3", f"{n}^3"),
                    "grid": [n, n, n], "nu": PHYS["nu"], "eta": PHYS["eta"], "d_i": PHYS["d_i"],
                    "j_mode": "moment", "layout": "aa (fluid and magnetic in place)",
-                   "forcing": "static, |k| <= 2, rms 1e-5"},
+                   "forcing": "static, |k| <= 2, rms 1e-5",
+                   "placement": f"fastest of up to {args.placement_trials} population buffers over a 3-step "
+                                "probe each (trial timings in the variants' placement_trials_ms)"},
         "roofline": {"bound": "hbm", "achieved": round(head["achieved_GBps"], 1), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(head["achieved_GBps"] / HBM_PEAK_GBPS, 4),
                      "traffic": traffic, "traffic_unit": "GB per launch (measured HBM bytes)",

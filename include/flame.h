@@ -70,6 +70,19 @@ typedef int32_t flame_status;
 #define FLAME_LAYOUT_AB 0
 #define FLAME_LAYOUT_AA 1
 
+/* Fluid collision. CENTRAL is the paper's central-moment collision (Sec. 3.1.2,
+ * S = diag[1,1,1,1,omega x5,1 x18]); BGK is the standard single-rate operator of Sec. 3.1.1,
+ * the same step with S = omega I (every central moment relaxed at omega, the body force still
+ * ending the first central moments at +F/2). */
+#define FLAME_COLLISION_CENTRAL 0
+#define FLAME_COLLISION_BGK 1
+
+/* Magnetic equilibrium. HALL is eq. gHall_eq with V = U - alpha_H J; EMHD is the electron-MHD
+ * variant of Sec. 6, with the bulk velocity neglected against the Hall current (V = -alpha_H J)
+ * in the equilibrium, in the J system of the moment route and in the initial state. */
+#define FLAME_MAGNETIC_HALL 0
+#define FLAME_MAGNETIC_EMHD 1
+
 /* Reduction slots of flame_reduce (FP64):
  *  0 E_kin = 1/2 <|u|^2>        1 E_mag = 1/2 <|B - b0|^2>     2 H_c = <u . (B - b0)>
  *  3 <|J|^2>                    4 max |div B|                  5 rms div B
@@ -96,6 +109,9 @@ typedef struct {
    * stay valid while the context lives). Each step adds F to the momentum and S to B. */
   const void* force_u;
   const void* force_b;
+  int32_t collision;    /* FLAME_COLLISION_CENTRAL (0, the paper's) / FLAME_COLLISION_BGK */
+  int32_t magnetic;     /* FLAME_MAGNETIC_HALL (0, the paper's) / FLAME_MAGNETIC_EMHD; the reverse-mode
+                           and trace entry points accept only the defaults (FLAME_E_UNSUPPORTED) */
 } flame_params;
 
 typedef struct flame_ctx flame_ctx;

@@ -23,6 +23,8 @@ FLAME_W_CFL = 1
 FLAME_F64, FLAME_F32, FLAME_F16 = 0, 1, 2
 FLAME_J_MOMENT, FLAME_J_STENCIL = 0, 1
 FLAME_LAYOUT_AB, FLAME_LAYOUT_AA = 0, 1
+FLAME_COLLISION_CENTRAL, FLAME_COLLISION_BGK = 0, 1
+FLAME_MAGNETIC_HALL, FLAME_MAGNETIC_EMHD = 0, 1
 FLAME_NRED = 16
 
 
@@ -34,6 +36,7 @@ class flame_params(ctypes.Structure):
         ("storage", ctypes.c_int32), ("jmode", ctypes.c_int32), ("layout", ctypes.c_int32),
         ("init_noneq", ctypes.c_int32),
         ("force_u", ctypes.c_void_p), ("force_b", ctypes.c_void_p),
+        ("collision", ctypes.c_int32), ("magnetic", ctypes.c_int32),
     ]
 
 

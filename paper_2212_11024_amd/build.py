@@ -29,13 +29,20 @@ def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
               # packed FP32 instructions stay off: hipcc must not emit v_pk_* FP32 forms
               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
               "-munsafe-fp-atomics", "-Wno-unused-command-line-argument", *[f"-D{d}" for d in defines]]
-    for src in SOURCES:
+    procs = []
+    for src in SOURCES:          # the translation units compile in parallel
         obj = os.path.join(CSRC, os.path.splitext(src)[0] + f".{os.getpid()}.o")
         cmd = [hipcc(), *common, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
+        procs.append((subprocess.Popen(cmd), cmd))
         objs.append(obj)
+    failed = [cmd for proc, cmd in procs if proc.wait() != 0]
+    if failed:
+        for o in objs:
+            if os.path.exists(o):
+                os.remove(o)
+        raise subprocess.CalledProcessError(1, failed[0])
     tmp = out + ".tmp"
     cmd = [hipcc(), "-shared", f"--offload-arch={ARCH}", "-fPIC", *objs, "-o", tmp,
            "-L/opt/rocm/lib", "-lhipfft", "-Wl,-rpath,/opt/rocm/lib"]

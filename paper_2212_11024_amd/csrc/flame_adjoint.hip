@@ -315,6 +315,10 @@ extern "C" {
 
 flame_status flame_step_save(flame_ctx* c, void* state) {
   if (!c) return FLAME_E_INVAL;
+  if (step_model(c->p) != 0) {
+    c->err = "reverse mode is built for the paper's model only (central-moment fluid, Hall equilibrium)";
+    return FLAME_E_UNSUPPORTED;
+  }
   if (!state) {
     c->err = "state is NULL";
     return FLAME_E_INVAL;
@@ -335,6 +339,10 @@ flame_status flame_step_save(flame_ctx* c, void* state) {
 
 flame_status flame_trace_step(flame_ctx* c, const void* src, void* dst) {
   if (!c) return FLAME_E_INVAL;
+  if (step_model(c->p) != 0) {
+    c->err = "reverse mode is built for the paper's model only (central-moment fluid, Hall equilibrium)";
+    return FLAME_E_UNSUPPORTED;
+  }
   if (c->p.jmode != FLAME_J_MOMENT) {
     c->err = "trace step is available on the moment route only";
     return FLAME_E_UNSUPPORTED;
@@ -361,6 +369,10 @@ flame_status flame_trace_step(flame_ctx* c, const void* src, void* dst) {
 
 flame_status flame_adjoint_step(flame_ctx* c, const void* state, const void* lam_next, void* lam, void* lam_j) {
   if (!c) return FLAME_E_INVAL;
+  if (step_model(c->p) != 0) {
+    c->err = "reverse mode is built for the paper's model only (central-moment fluid, Hall equilibrium)";
+    return FLAME_E_UNSUPPORTED;
+  }
   if (!state || !lam_next || !lam || lam == lam_next || (c->p.jmode == FLAME_J_STENCIL && !lam_j)) {
     c->err = "adjoint step needs state, lam_next and a distinct lam (and lam_j for the stencil route)";
     return FLAME_E_INVAL;
@@ -376,6 +388,10 @@ flame_status flame_adjoint_step(flame_ctx* c, const void* state, const void* lam
 
 flame_status flame_adjoint_trace_step(flame_ctx* c, const void* src, const void* lam_next, void* lam) {
   if (!c) return FLAME_E_INVAL;
+  if (step_model(c->p) != 0) {
+    c->err = "reverse mode is built for the paper's model only (central-moment fluid, Hall equilibrium)";
+    return FLAME_E_UNSUPPORTED;
+  }
   if (c->p.jmode != FLAME_J_MOMENT) {
     c->err = "the trace adjoint is available on the moment route only";
     return FLAME_E_UNSUPPORTED;
@@ -401,6 +417,10 @@ flame_status flame_adjoint_init(flame_ctx* c, const void* lam0, const double* u,
                                 const double* grad_u, const double* grad_b, double* g_u, double* g_b,
                                 double* g_grad_u, double* g_grad_b) {
   if (!c) return FLAME_E_INVAL;
+  if (step_model(c->p) != 0) {
+    c->err = "reverse mode is built for the paper's model only (central-moment fluid, Hall equilibrium)";
+    return FLAME_E_UNSUPPORTED;
+  }
   if (!lam0 || !u || !b || !g_u || !g_b) {
     c->err = "adjoint init needs lam0, u, b, g_u and g_b";
     return FLAME_E_INVAL;

@@ -94,6 +94,7 @@ struct AuxArgs {
   double b0[3];
   double alpha, omega_b;
   int stencil;
+  int emhd;     // electron MHD: J from the moments with the bulk velocity taken as zero
 };
 
 template <typename S>
@@ -140,7 +141,8 @@ __device__ NodeQ node_quantities(const AuxArgs<S>& a, int x, int y, int z) {
     q.B[c] = a.b0[c] + q.b[c];
   }
   if (!a.stencil) {
-    current_from_moments(lam, q.U, q.B, a.alpha, a.omega_b, q.J);
+    const double zero[3] = {0.0, 0.0, 0.0};
+    current_from_moments(lam, a.emhd ? zero : q.U, q.B, a.alpha, a.omega_b, q.J);
   } else {
     const int xp = wrap(x + 1, v.nx), xm = wrap(x - 1, v.nx);
     const int yp = wrap(y + 1, v.ny), ym = wrap(y - 1, v.ny);
@@ -178,6 +180,7 @@ struct InitArgs {
   double b0[3];
   double omega, omega_b, alpha;
   int noneq;
+  int emhd;
   int nx, ny, nz;
   size_t n;
   size_t stride;
@@ -238,6 +241,7 @@ __global__ __launch_bounds__(256) void init_kernel(InitArgs<S> a) {
   fl.fluid_noneq = a.noneq && have_gu;
   fl.mag_noneq = a.noneq && have_gb;
   fl.has_H = have_gb;
+  fl.emhd = a.emhd != 0;
   double f[kQ], g[kM];
   init_node(U, b, gu, gb, F, Sb, k, fl, f, g);
   for (int i = 0; i < kQ; ++i)
@@ -616,6 +620,8 @@ std::string validate(const flame_params* p) {
     return "unknown storage";
   if (p->jmode != FLAME_J_MOMENT && p->jmode != FLAME_J_STENCIL) return "unknown jmode";
   if (p->layout != FLAME_LAYOUT_AB && p->layout != FLAME_LAYOUT_AA) return "unknown layout";
+  if (p->collision != FLAME_COLLISION_CENTRAL && p->collision != FLAME_COLLISION_BGK) return "unknown collision";
+  if (p->magnetic != FLAME_MAGNETIC_HALL && p->magnetic != FLAME_MAGNETIC_EMHD) return "unknown magnetic model";
   return "";
 }
 
@@ -651,6 +657,7 @@ AuxArgs<S> make_aux(const flame_ctx* c) {
   a.alpha = c->p.d_i;
   a.omega_b = c->omega_b;
   a.stencil = c->p.jmode == FLAME_J_STENCIL;
+  a.emhd = c->p.magnetic == FLAME_MAGNETIC_EMHD;
   return a;
 }
 
@@ -821,6 +828,7 @@ flame_status flame_init(const flame_params* p, const double* u, const double* b,
     a.omega_b = c->omega_b;
     a.alpha = p->d_i;
     a.noneq = p->init_noneq;
+    a.emhd = p->magnetic == FLAME_MAGNETIC_EMHD;
     a.nx = p->nx;
     a.ny = p->ny;
     a.nz = p->nz;
@@ -1156,6 +1164,8 @@ flame_status flame_trace_export(flame_ctx* c, void* lat) {
   if (!lat) return fail(c, FLAME_E_INVAL, "lat is NULL");
   if (c->p.layout != FLAME_LAYOUT_AA || c->p.jmode != FLAME_J_MOMENT)
     return fail(c, FLAME_E_UNSUPPORTED, "trace export is available on the moment route with the AA layout only");
+  if (step_model(c->p) != 0)
+    return fail(c, FLAME_E_UNSUPPORTED, "reverse mode is built for the paper's model only");
   hipError_t e = by_storage(c, [&](auto tag) {
     using S = decltype(tag);
     hipLaunchKernelGGL(export_kernel<S>, dim3(blocks_for(c->n, 256)), dim3(256), 0, c->stream, make_view<S>(c),

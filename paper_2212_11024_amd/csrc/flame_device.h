@@ -309,6 +309,37 @@ FLAME_HD void collide_magnetic(R (&g)[kM], const R (&U)[3], const R (&B)[3],
 
 // ------------------------------------------------------------------ per-node reverse pass
 // Derivatives of the 1-D factors of Axis with respect to u (h2 is constant).
+// BGK variant of the fluid collision, in place on deviations: the central-moment step with every
+// rate equal to w (Sec. 3.1.2; the standard operator of Sec. 3.1.1),
+//   f*_i = f^mhd(0)_i + (1 - w)(f_i - f^mhd(0)_i) + (1 - w/2) sum_a F_a H^a_i.
+// The force term ends the first central moments at +F/2 as in collide_fluid: before the
+// collision those of f - f^mhd(0) are -F/2 (U carries F/2), and (1 - w) of them survive.
+// f^mhd(0) - f_rest is the same equilibrium deviation as in collide_fluid.
+template <typename R>
+FLAME_HD void collide_fluid_bgk(R (&f)[kQ], const FluidMoments<R>& m, const R (&U)[3], const R (&b)[3],
+                                const R (&b0)[3], const R (&F)[3], R omega) {
+  const R s = b0[0] * b[0] + b0[1] * b[1] + b0[2] * b[2] + R(0.5) * (b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+  const Axis<R> ax(U[0]), ay(U[1]), az(U[2]);
+  const R drho = m.drho;
+  const R om1 = R(1) - omega;
+  const R fk = R(1) - R(0.5) * omega;
+  const R fx = fk * F[0], fy = fk * F[1], fz = fk * F[2];
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) {
+    const int x = cq(i, 0) + 1, y = cq(i, 1) + 1, z = cq(i, 2) + 1;
+    const R ex = ax.e[x], ey = ay.e[y], ez = az.e[z];
+    const R em1 = ex + (R(1) + ex) * (ey + (R(1) + ey) * ez);   // E_i - 1 without cancellation
+    const R w = R(wq(i));
+    R eq = w * (drho * (R(1) + em1) + em1);
+    const R bc = R(cq(i, 0)) * b[0] + R(cq(i, 1)) * b[1] + R(cq(i, 2)) * b[2];
+    const R b0c = R(cq(i, 0)) * b0[0] + R(cq(i, 1)) * b0[1] + R(cq(i, 2)) * b0[2];
+    eq += (w * R(4.5)) * (s * R(speed2q(i) - 1.0 / 3.0) - bc * (R(2) * b0c + bc));
+    const R force = ax.h1[x] * ay.h0[y] * az.h0[z] * fx + ax.h0[x] * ay.h1[y] * az.h0[z] * fy
+                  + ax.h0[x] * ay.h0[y] * az.h1[z] * fz;
+    f[i] = eq + om1 * (f[i] - eq) + force;
+  }
+}
+
 template <typename R>
 struct AxisD {
   R de[3], dh0[3], dh1[3];
@@ -527,12 +558,14 @@ FLAME_HD void collide_vjp(const R (&f)[kQ], const R (&g)[kM], const R (&F)[3], c
 // ------------------------------------------------------------------ initial state of a node
 // Deviations of the initial populations at a node (rho = 1): fluid f^mhd(0)(1, u, B) plus the
 // first-order non-equilibrium stress P0 = -(c_s^2 / w)(G + G^T - 2/3 tr G I), G = grad u, and
-// -F/2 first central moment; magnetic g^Hall(0)(u, B, curl b) - (1/w_B) W_i xi_ia d_a b_c - S/2 W_i.
+// -F/2 first central moment; magnetic g^Hall(0)(u, B, curl b) - (1/w_B) W_i xi_ia d_a b_c - S/2 W_i
+// (with u taken as zero in g^Hall(0) for electron MHD).
 // G[a][c] = d u_c / d x_a, H[a][c] = d b_c / d x_a (ignored unless the flags say present).
 struct InitFlags {
   bool fluid_noneq;   // add the fluid non-equilibrium stress (needs G)
   bool mag_noneq;     // add the magnetic non-equilibrium part (needs H)
   bool has_H;         // J = curl b from H (else J = 0)
+  bool emhd = false;  // electron MHD: the magnetic equilibrium without the bulk velocity
 };
 
 FLAME_HD void init_node(const double (&u)[3], const double (&b)[3], const double (&G)[3][3],
@@ -571,7 +604,8 @@ FLAME_HD void init_node(const double (&u)[3], const double (&b)[3], const double
     J[1] = H[2][0] - H[0][2];
     J[2] = H[0][1] - H[1][0];
   }
-  const double V[3] = {u[0] - k.alpha * J[0], u[1] - k.alpha * J[1], u[2] - k.alpha * J[2]};
+  const double um = fl.emhd ? 0.0 : 1.0;
+  const double V[3] = {um * u[0] - k.alpha * J[0], um * u[1] - k.alpha * J[1], um * u[2] - k.alpha * J[2]};
   for (int i = 0; i < 7; ++i)
     for (int c = 0; c < 3; ++c) {
       double xv = 0, xb = 0, xg = 0;

@@ -63,6 +63,10 @@ inline size_t population_stride(const flame_params& p) {
   const size_t align = 256 / vb;
   return (n + align - 1) / align * align + FLAME_STRIDE_PAD_BYTES / vb;
 }
+// Model bits of the step kernels: 1 = BGK fluid collision, 2 = electron MHD; 0 is the paper's.
+inline int step_model(const flame_params& p) {
+  return (p.collision == FLAME_COLLISION_BGK ? 1 : 0) | (p.magnetic == FLAME_MAGNETIC_EMHD ? 2 : 0);
+}
 inline bool mag_two_lattice(const flame_params& p) {
   return p.layout == FLAME_LAYOUT_AB || p.jmode == FLAME_J_STENCIL;
 }

@@ -160,16 +160,37 @@ __device__ __forceinline__ void forcing_at(const StepArgs<S>& a, uint32_t cell, 
   }
 }
 
+// Model variants, chosen at compile time (0 is the paper's scheme): bit kModelBGK, the BGK fluid
+// collision (S = omega I); bit kModelEMHD, electron MHD (the magnetic equilibrium and the J
+// system see a zero bulk velocity).
+constexpr int kModelBGK = 1;
+constexpr int kModelEMHD = 2;
+
+template <typename R>
+struct Zero3 {
+  R v[3] = {R(0), R(0), R(0)};
+};
+
+// Fluid collision of the model, in place.
+template <int MODEL, bool Grouped, typename R>
+__device__ __forceinline__ void collide_fluid_model(R (&f)[kQ], const FluidMoments<R>& m, const R (&U)[3],
+                                                    const R (&b)[3], const R (&b0)[3], const R (&F)[3], R omega) {
+  if constexpr ((MODEL & kModelBGK) != 0)
+    collide_fluid_bgk(f, m, U, b, b0, F, omega);
+  else
+    collide_fluid<R, Grouped>(f, m, R(1) + m.drho, U, b, b0, F, omega);
+}
+
 // Node update from loaded populations and J: moments, both collisions, in place in f and g.
-template <bool Grouped, typename R>
+// Um is the bulk velocity as the magnetic equilibrium sees it (zero for electron MHD).
+template <int MODEL, bool Grouped, typename R>
 __device__ __forceinline__ void collide_node(R (&f)[kQ], R (&g)[kM], const FluidMoments<R>& m, const R (&U)[3],
-                                             const R (&b)[3], const R (&J)[3], const R (&F)[3], const R (&Sb)[3],
-                                             const PhysConst<R>& k) {
-  const R rho = R(1) + m.drho;
+                                             const R (&Um)[3], const R (&b)[3], const R (&J)[3], const R (&F)[3],
+                                             const R (&Sb)[3], const PhysConst<R>& k) {
   const R b0[3] = {k.b0[0], k.b0[1], k.b0[2]};
   const R B[3] = {b0[0] + b[0], b0[1] + b[1], b0[2] + b[2]};
-  collide_fluid<R, Grouped>(f, m, rho, U, b, b0, F, k.omega);
-  collide_magnetic(g, U, B, b, J, Sb, k.alpha, k.omega_b);
+  collide_fluid_model<MODEL, Grouped>(f, m, U, b, b0, F, k.omega);
+  collide_magnetic(g, Um, B, b, J, Sb, k.alpha, k.omega_b);
 }
 
 // Record the node's pre-collision deviations (and the J it uses) for the adjoint.
@@ -189,7 +210,7 @@ __device__ __forceinline__ void save_current(R* save, size_t n, uint32_t cell, c
 // ------------------------------------------------------------------ moment-route kernel
 constexpr int kLocalThreads = 256;
 
-template <typename S, bool FAA, bool MAA, int PAR, bool SAVE>
+template <typename S, bool FAA, bool MAA, int PAR, bool SAVE, int MODEL>
 __global__ __launch_bounds__(kLocalThreads) void step_local(StepArgs<S> a) {
   using R = typename Enc<S>::R;
   unsigned bx, by, bz;
@@ -216,10 +237,12 @@ __global__ __launch_bounds__(kLocalThreads) void step_local(StepArgs<S> a) {
 #pragma unroll
   for (int c = 0; c < 3; ++c) b[c] = b_component(g, c, R(0.5) * Sb[c]);
   const R B[3] = {a.k.b0[0] + b[0], a.k.b0[1] + b[1], a.k.b0[2] + b[2]};
+  const Zero3<R> zero;
+  const R(&Um)[3] = (MODEL & kModelEMHD) != 0 ? zero.v : U;
   R J[3];
-  current_from_moments(lam, U, B, a.k.alpha, a.k.omega_b, J);
+  current_from_moments(lam, Um, B, a.k.alpha, a.k.omega_b, J);
   if (SAVE) save_current(a.save, a.n, cell, J);
-  collide_node<sizeof(S) == 2>(f, g, m, U, b, J, F, Sb, a.k);
+  collide_node<MODEL, sizeof(S) == 2>(f, g, m, U, Um, b, J, F, Sb, a.k);
   store_fluid<S, FAA, PAR>(a, rw, pl, f);
   store_magnetic<S, MAA, PAR>(a, rw, pl, g);
 }
@@ -245,7 +268,7 @@ struct Tile {
 };
 constexpr int kZChunk = FLAME_ZCHUNK;   // planes per workgroup
 
-template <typename S, bool FAA, int PAR, bool SAVE>
+template <typename S, bool FAA, int PAR, bool SAVE, int MODEL>
 __global__ __launch_bounds__(kTX * Tile<typename Enc<S>::R>::ty, FLAME_ZMARCH_WAVES_PER_EU) void step_zmarch(
     StepArgs<S> a) {
   using E = Enc<S>;
@@ -345,7 +368,7 @@ __global__ __launch_bounds__(kTX * Tile<typename Enc<S>::R>::ty, FLAME_ZMARCH_WA
 #pragma unroll
       for (int c = 0; c < 3; ++c) b[c] = b_component(g, c, R(0.5) * Sb[c]);
       const R b0[3] = {a.k.b0[0], a.k.b0[1], a.k.b0[2]};
-      collide_fluid(f, m, R(1) + m.drho, U, b, b0, F, a.k.omega);
+      collide_fluid_model<MODEL, false>(f, m, U, b, b0, F, a.k.omega);
       store_fluid<S, FAA, PAR>(a, rw, pl, f);
     }
     __syncthreads();
@@ -360,7 +383,8 @@ __global__ __launch_bounds__(kTX * Tile<typename Enc<S>::R>::ty, FLAME_ZMARCH_WA
       J[2] = R(0.5) * (C[py][px + 1][1] - C[py][px - 1][1]) - R(0.5) * (C[py + 1][px][0] - C[py - 1][px][0]);
       const R B[3] = {a.k.b0[0] + b[0], a.k.b0[1] + b[1], a.k.b0[2] + b[2]};
       if (SAVE) save_current(a.save, a.n, cell, J);
-      collide_magnetic(g, U, B, b, J, Sb, a.k.alpha, a.k.omega_b);
+      const Zero3<R> zero;
+      collide_magnetic(g, (MODEL & kModelEMHD) != 0 ? zero.v : U, B, b, J, Sb, a.k.alpha, a.k.omega_b);
       store_magnetic<S, false, 0>(a, rw, pl, g);
     }
     const int t = prev;
@@ -368,6 +392,33 @@ __global__ __launch_bounds__(kTX * Tile<typename Enc<S>::R>::ty, FLAME_ZMARCH_WA
     cur = next;
     next = spare;
     spare = t;
+  }
+}
+
+template <typename S, bool SAVE, int MODEL>
+static void launch_model(const flame_ctx* c, const SetPtrs& s, const StepArgs<S>& a) {
+  using R = typename Enc<S>::R;
+  const int par = c->parity;
+  if (c->p.jmode == FLAME_J_STENCIL) {
+    constexpr int kTY = Tile<R>::ty;
+    const dim3 block(kTX, kTY, 1);
+    const dim3 grid(((c->p.nx + kTX - 1) / kTX) * ((c->p.ny + kTY - 1) / kTY) * ((c->p.nz + a.zchunk - 1) / a.zchunk));
+    if (!s.fluid_aa)
+      hipLaunchKernelGGL((step_zmarch<S, false, 0, SAVE, MODEL>), grid, block, 0, c->stream, a);
+    else if (par == 0)
+      hipLaunchKernelGGL((step_zmarch<S, true, 0, SAVE, MODEL>), grid, block, 0, c->stream, a);
+    else
+      hipLaunchKernelGGL((step_zmarch<S, true, 1, SAVE, MODEL>), grid, block, 0, c->stream, a);
+  } else {
+    const unsigned tx = row_threads(c->p.nx);
+    const dim3 block(tx, 1, 1);
+    const dim3 grid(((c->p.nx + tx - 1) / tx) * c->p.ny * c->p.nz);
+    if (!s.fluid_aa)
+      hipLaunchKernelGGL((step_local<S, false, false, 0, SAVE, MODEL>), grid, block, 0, c->stream, a);
+    else if (par == 0)
+      hipLaunchKernelGGL((step_local<S, true, true, 0, SAVE, MODEL>), grid, block, 0, c->stream, a);
+    else
+      hipLaunchKernelGGL((step_local<S, true, true, 1, SAVE, MODEL>), grid, block, 0, c->stream, a);
   }
 }
 
@@ -391,29 +442,19 @@ static hipError_t launch_typed(const flame_ctx* c, const SetPtrs& s, size_t stri
   a.k.omega_b = R(c->omega_b);
   a.k.alpha = R(c->p.d_i);
   for (int i = 0; i < 3; ++i) a.k.b0[i] = R(c->p.b0[i]);
-  const int par = c->parity;
-  if (c->p.jmode == FLAME_J_STENCIL) {
-    constexpr int kTY = Tile<R>::ty;
-    a.zchunk = std::min(c->p.nz, kZChunk);
-    const dim3 block(kTX, kTY, 1);
-    const dim3 grid(((c->p.nx + kTX - 1) / kTX) * ((c->p.ny + kTY - 1) / kTY) * ((c->p.nz + a.zchunk - 1) / a.zchunk));
-    if (!s.fluid_aa)
-      hipLaunchKernelGGL((step_zmarch<S, false, 0, SAVE>), grid, block, 0, c->stream, a);
-    else if (par == 0)
-      hipLaunchKernelGGL((step_zmarch<S, true, 0, SAVE>), grid, block, 0, c->stream, a);
-    else
-      hipLaunchKernelGGL((step_zmarch<S, true, 1, SAVE>), grid, block, 0, c->stream, a);
+  a.zchunk = c->p.jmode == FLAME_J_STENCIL ? std::min(c->p.nz, kZChunk) : 1;
+  const int model = step_model(c->p);
+  if constexpr (SAVE) {
+    // the state-saving steps serve the adjoint, which is built for the paper's model only
+    if (model != 0) return hipErrorInvalidValue;
+    launch_model<S, true, 0>(c, s, a);
   } else {
-    a.zchunk = 1;
-    const unsigned tx = row_threads(c->p.nx);
-    const dim3 block(tx, 1, 1);
-    const dim3 grid(((c->p.nx + tx - 1) / tx) * c->p.ny * c->p.nz);
-    if (!s.fluid_aa)
-      hipLaunchKernelGGL((step_local<S, false, false, 0, SAVE>), grid, block, 0, c->stream, a);
-    else if (par == 0)
-      hipLaunchKernelGGL((step_local<S, true, true, 0, SAVE>), grid, block, 0, c->stream, a);
-    else
-      hipLaunchKernelGGL((step_local<S, true, true, 1, SAVE>), grid, block, 0, c->stream, a);
+    switch (model) {
+      case 0: launch_model<S, false, 0>(c, s, a); break;
+      case kModelBGK: launch_model<S, false, kModelBGK>(c, s, a); break;
+      case kModelEMHD: launch_model<S, false, kModelEMHD>(c, s, a); break;
+      default: launch_model<S, false, kModelBGK | kModelEMHD>(c, s, a); break;
+    }
   }
   return hipGetLastError();
 }

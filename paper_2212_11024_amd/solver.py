@@ -13,6 +13,8 @@ from . import _lib as L
 STORAGE = {"f64": L.FLAME_F64, "f32": L.FLAME_F32, "f16": L.FLAME_F16}
 JMODE = {"moment": L.FLAME_J_MOMENT, "stencil": L.FLAME_J_STENCIL}
 LAYOUT = {"ab": L.FLAME_LAYOUT_AB, "aa": L.FLAME_LAYOUT_AA}
+COLLISION = {"central": L.FLAME_COLLISION_CENTRAL, "bgk": L.FLAME_COLLISION_BGK}
+MAGNETIC = {"hall": L.FLAME_MAGNETIC_HALL, "emhd": L.FLAME_MAGNETIC_EMHD}
 
 
 def _ptr(t):
@@ -27,11 +29,20 @@ class Solver:
     init_noneq a None gradient is taken by central differences on the grid.
     force_u, force_b: (3, nz, ny, nx) static forcing (any float dtype; converted to the
     storage's arithmetic type: float64 for "f64", float32 otherwise), or None.
+    collision: "central" (the paper's) or "bgk"; magnetic: "hall" (the paper's) or "emhd"
+    (electron MHD); the variants run forward only.
+    placement_trials: the step's speed depends on the physical memory behind the population
+    storage (at 512^3 FP32 one allocation runs at 9.1-9.4 ms per step, another of the same size
+    and address at 10.5-10.8 ms: DRAM read latency at the L2 of about 2450 against 2800 cycles,
+    independent of the array padding). With k > 1 the solver holds up to k candidate buffers at
+    once (as many as fit in 80% of the free device memory), times a few steps on each from the
+    initial state, keeps the fastest and frees the others; placement_ms records the trials.
     """
 
     def __init__(self, nx, ny, nz, nu, eta, d_i=0.0, b0=(0.0, 0.0, 0.0), storage="f32",
                  jmode="moment", layout="aa", u=None, b=None, grad_u=None, grad_b=None,
-                 force_u=None, force_b=None, init_noneq=True, device="cuda"):
+                 force_u=None, force_b=None, init_noneq=True, device="cuda", collision="central",
+                 magnetic="hall", placement_trials=1):
         if not torch.cuda.is_available():
             raise RuntimeError("flame needs a HIP device (torch.cuda.is_available() is False)")
         L.load()
@@ -48,15 +59,13 @@ class Solver:
             p.b0[i] = float(b0[i])
         p.storage, p.jmode, p.layout = STORAGE[storage], JMODE[jmode], LAYOUT[layout]
         p.init_noneq = 1 if init_noneq else 0
+        p.collision, p.magnetic = COLLISION[collision], MAGNETIC[magnetic]
         p.force_u = _ptr(self.force_u) or None
         p.force_b = _ptr(self.force_b) or None
         self.params = p
         nbytes = L.flame_storage_bytes(p)
         if nbytes == 0:
             raise L.FlameError(L.FLAME_E_INVAL, "invalid parameters")
-        self.storage = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
-        if self.storage.data_ptr() % 256:
-            raise RuntimeError("population storage is not 256-byte aligned")
 
         def dev(t):
             return None if t is None else t.to(self.device, torch.float64).contiguous()
@@ -66,9 +75,44 @@ class Solver:
         b = dev(b) if b is not None else zero
         gu, gb = dev(grad_u), dev(grad_b)
         self.stream = torch.cuda.current_stream(self.device)
-        self.status, self.ctx = L.flame_init(p, _ptr(u), _ptr(b), _ptr(gu), _ptr(gb), _ptr(self.storage),
-                                             nbytes, self.stream.cuda_stream)
+        init = lambda buf: L.flame_init(p, _ptr(u), _ptr(b), _ptr(gu), _ptr(gb), _ptr(buf), nbytes,  # noqa: E731
+                                        self.stream.cuda_stream)
+        self.placement_ms = None
+        if placement_trials > 1:
+            self.storage, self.placement_ms = self._fastest_storage(init, nbytes, placement_trials)
+        else:
+            self.storage = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        if self.storage.data_ptr() % 256:
+            raise RuntimeError("population storage is not 256-byte aligned")
+        self.status, self.ctx = init(self.storage)
         self.stream.synchronize()     # the inputs may be released after this point
+
+    def _fastest_storage(self, init, nbytes, trials, warm=2, timed=3):
+        """Candidate buffers held at once (so each has its own physical memory); each is
+        initialised and timed over a few steps; the fastest is returned with all timings (ms per
+        step), the others are released."""
+        free, _ = torch.cuda.mem_get_info(self.device)
+        k = max(1, min(int(trials), int(0.8 * free) // nbytes))
+        cands = [torch.empty(nbytes, dtype=torch.uint8, device=self.device) for _ in range(k)]
+        times = []
+        for buf in cands:
+            _, ctx = init(buf)
+            try:
+                L.flame_step(ctx, warm)
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(self.stream)
+                L.flame_step(ctx, timed)
+                e1.record(self.stream)
+                e1.synchronize()
+                times.append(e0.elapsed_time(e1) / timed)
+            finally:
+                L.flame_destroy(ctx)
+        best = min(range(k), key=times.__getitem__)
+        keep = cands[best]
+        del cands
+        torch.cuda.empty_cache()
+        return keep, times
 
     # -- time stepping
     def step(self, n=1):

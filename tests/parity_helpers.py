@@ -76,7 +76,7 @@ def gpu_solver(case: Case, storage="f64", layout="aa", noneq=True):
     from paper_2212_11024_amd.solver import Solver
     u, gu, b, gb, fu, fb = inputs(case)
     return Solver(case.nx, case.ny, case.nz, case.nu, case.eta, case.d_i, case.b0, storage, case.jmode, layout,
-                  u, b, gu, gb, fu, fb, init_noneq=noneq)
+                  u, b, gu, gb, fu, fb, init_noneq=noneq, collision=case.collision, magnetic=case.magnetic)
 
 
 def deviation_error(solver, p, st):

@@ -46,6 +46,8 @@ def _params(**kw):
     p.storage = kw.get("storage", L.FLAME_F32)
     p.jmode = kw.get("jmode", L.FLAME_J_MOMENT)
     p.layout = kw.get("layout", L.FLAME_LAYOUT_AA)
+    p.collision = kw.get("collision", L.FLAME_COLLISION_CENTRAL)
+    p.magnetic = kw.get("magnetic", L.FLAME_MAGNETIC_HALL)
     return p
 
 
@@ -57,6 +59,14 @@ def test_storage_bytes(lib):
     assert L.flame_storage_bytes(_params(storage=L.FLAME_F64)) == 48 * 8 * n
     assert L.flame_storage_bytes(_params(storage=L.FLAME_F16)) == 48 * 2 * n
     assert L.flame_storage_bytes(_params(shape=(512, 512, 512))) == 48 * 4 * 512 ** 3
+
+
+def test_model_variants_are_valid_parameters(lib):
+    # the BGK fluid and electron-MHD variants change no storage size
+    n = 8 * 8 * 8
+    for coll in (L.FLAME_COLLISION_CENTRAL, L.FLAME_COLLISION_BGK):
+        for mag in (L.FLAME_MAGNETIC_HALL, L.FLAME_MAGNETIC_EMHD):
+            assert L.flame_storage_bytes(_params(collision=coll, magnetic=mag)) == 48 * 4 * n
 
 
 def test_array_size_limit(lib):
@@ -77,7 +87,8 @@ def test_array_size_limit(lib):
 @pytest.mark.parametrize("kw,msg", [
     ({"nu": 0.0}, "nu"), ({"eta": -1.0}, "eta"), ({"d_i": -2.0}, "d_i"), ({"shape": (0, 4, 4)}, "grid"),
     ({"shape": (2, 8, 8), "jmode": L.FLAME_J_STENCIL}, "stencil"), ({"storage": 7}, "storage"),
-    ({"layout": 9}, "layout"), ({"nu": float("nan")}, "nu"),
+    ({"layout": 9}, "layout"), ({"nu": float("nan")}, "nu"), ({"collision": 2}, "collision"),
+    ({"magnetic": -1}, "magnetic"),
 ])
 def test_invalid_parameters_rejected_before_device_use(lib, kw, msg):
     p = _params(**kw)

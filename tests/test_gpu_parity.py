@@ -32,6 +32,10 @@ CASES = {
     "long_x": Case(257, 3, 3, jmode="moment", forced=True, seed=9),
     # the Orszag-Tang vortex of the paper's turbulence runs (Sec. 4.4, Sec. 5), ragged grid
     "orszag_tang": Case(13, 10, 9, jmode="moment", d_i=2.0, b0=(0.0, 0.0, 0.0), ic="orszag_tang"),
+    # model variants: BGK fluid collision (S = omega I), electron MHD (Sec. 6), and both
+    "bgk": Case(13, 10, 9, jmode="moment", forced=True, seed=23, collision="bgk"),
+    "emhd": Case(13, 10, 9, jmode="moment", forced=True, seed=25, magnetic="emhd"),
+    "bgk_emhd_stencil": Case(12, 8, 8, jmode="stencil", seed=27, collision="bgk", magnetic="emhd"),
 }
 
 
@@ -78,7 +82,8 @@ def test_fp64_parity_100_steps(jmode, ic):
 
 
 @pytest.mark.parametrize("layout", ["ab", "aa"])
-@pytest.mark.parametrize("name", ["ragged_moment", "ragged_stencil", "forced", "orszag_tang"])
+@pytest.mark.parametrize("name", ["ragged_moment", "ragged_stencil", "forced", "orszag_tang", "bgk", "emhd",
+                                  "bgk_emhd_stencil"])
 def test_fp32_step_parity_100_steps(name, layout):
     case = CASES[name]
     _print_case(name, layout=layout, storage="f32", steps=100)
@@ -359,3 +364,52 @@ def test_one_node_thick_grid():
     st = scheme.step(scheme.init_state(p, u, b, gu, gb), p, 21)
     s.step(21)
     assert deviation_error(s, p, st) < 1e-12
+
+
+@pytest.mark.parametrize("name", ["bgk", "emhd", "bgk_emhd_stencil"])
+def test_variant_fp64_parity_100_steps(name):
+    # the model variants over 100 steps against the extended evaluation of the oracle
+    case = CASES[name]
+    _print_case(name, storage="f64", steps=100)
+    s = gpu_solver(case, "f64", "aa")
+    s.step(100)
+    assert extended_error(s, extended_run(case, 100)) < TOL["f64"]
+
+
+def test_reverse_mode_refuses_model_variants():
+    """Host-side refusals: the state-saving step, the adjoint entry points and the trace calls
+    are built for the paper's model only."""
+    from paper_2212_11024_amd import _lib as L
+    for kw in ({"collision": "bgk"}, {"magnetic": "emhd"}):
+        case = Case(8, 6, 5, jmode="moment", **kw)
+        s = gpu_solver(case, "f32", "aa")
+        buf = torch.empty(51 * s.n * 4, dtype=torch.uint8, device=s.device)
+        lat = torch.empty((2, L.flame_trace_bytes(s.ctx)), dtype=torch.uint8, device=s.device)
+        calls = (lambda: L.flame_step_save(s.ctx, buf.data_ptr()),
+                 lambda: L.flame_trace_export(s.ctx, lat[0].data_ptr()),
+                 lambda: L.flame_trace_step(s.ctx, lat[0].data_ptr(), lat[1].data_ptr()))
+        for call in calls:
+            with pytest.raises(L.FlameError) as e:
+                call()
+            assert e.value.code == L.FLAME_E_UNSUPPORTED
+        s.close()
+
+
+def test_placement_probe_keeps_results():
+    """Choosing the population buffer by timing trial steps on candidates changes nothing in the
+    run: the kept buffer is re-initialised, and the state after some steps is bitwise that of a
+    run without the probe."""
+    from paper_2212_11024_amd.solver import Solver
+    case = Case(24, 20, 16, jmode="moment", forced=True, seed=29)
+    _print_case("placement probe", trials=3)
+    u, gu, b, gb, fu, fb = inputs(case)
+    runs = []
+    for trials in (1, 3):
+        s = Solver(case.nx, case.ny, case.nz, case.nu, case.eta, case.d_i, case.b0, "f32", "moment", "aa",
+                   u, b, gu, gb, fu, fb, placement_trials=trials)
+        assert (s.placement_ms is None) if trials == 1 else (len(s.placement_ms) == 3)
+        s.step(9)
+        runs.append(s.get_populations())
+        s.close()
+    assert torch.equal(runs[0][0], runs[1][0]) and torch.equal(runs[0][1], runs[1][1])
+
