@@ -263,6 +263,45 @@ def test_degenerate_grids():
     assert torch.equal(f0, s.get_populations()[0])
 
 
+def _axis_limited_field(shape, seed, amp, nmodes=4):
+    """A few random Fourier modes with |k_a| <= (n_a - 1) / 2 on every axis (no aliasing, no
+    Nyquist content), for grids too thin for the shell fields."""
+    import itertools
+    lim = [(n - 1) // 2 for n in shape]
+    ks = [k for k in itertools.product(*(range(-m, m + 1) for m in lim))
+          if k[2] > 0 or (k[2] == 0 and (k[1] > 0 or (k[1] == 0 and k[0] > 0)))]
+    rng = np.random.default_rng(seed)
+    ks = [ks[i] for i in rng.permutation(len(ks))[:nmodes]]
+    v = amp * (rng.standard_normal((len(ks), 3)) + 1j * rng.standard_normal((len(ks), 3)))
+    return synthetic.ModeField(np.array(ks, dtype=np.int64).reshape(-1, 3), v)
+
+
+@pytest.mark.parametrize("shape", [(1, 12, 10), (1, 1, 16), (2, 3, 4), (5, 1, 6)])
+def test_spectral_diagnostics_on_degenerate_grids(shape):
+    """Energy spectra, dissipation spectra and transfer terms on one-node-thick axes and on the
+    smallest grids (length-2 and length-4 axes carry a Nyquist plane) against the oracle."""
+    from paper_2212_11024_amd.solver import Solver
+    _print_case("degenerate diagnostics", shape=shape)
+    u, gu = synthetic.evaluate(_axis_limited_field(shape, 41, 0.01), shape)
+    b, gb = synthetic.evaluate(_axis_limited_field(shape, 43, 0.01), shape)
+    nx, ny, nz = shape
+    p = scheme.Params(nx, ny, nz, 0.02, 0.03, 1.0, (0.01, 0.0, 0.02), "moment", "closed")
+    st = scheme.step(scheme.init_state(p, u, b, gu, gb), p, 3)
+    s = Solver(nx, ny, nz, p.nu, p.eta, p.d_i, p.b0, "f64", "moment", "aa", u, b, gu, gb)
+    s.step(3)
+    _, ou, oB, oJ, _ = scheme.fields(st, p)
+    ns = diagnostics.max_shell(p.shape)
+    for field, ref in (("u", ou), ("B", oB)):
+        e, eo = s.spectrum(field, ns), torch.tensor(diagnostics.spectrum(ref, ns))
+        d, do = s.dissipation_spectrum(field, ns), torch.tensor(diagnostics.dissipation_spectrum(ref, ns))
+        assert torch.allclose(e, eo, rtol=1e-10, atol=1e-20 + 1e-12 * float(eo.abs().max()))
+        assert torch.allclose(d, do, rtol=1e-10, atol=1e-20 + 1e-12 * float(do.abs().max()))
+    got = s.energy_transfer(ns)
+    ref = torch.tensor(np.stack(diagnostics.energy_transfer(ou, oB, oJ, ns)))
+    assert float((got - ref).abs().max()) <= 1e-11 * max(float(ref.abs().max()), 1e-30)
+    s.close()
+
+
 def test_nonfinite_detection():
     case = CASES["ragged_moment"]
     s = gpu_solver(case, "f32", "aa")
