@@ -12,6 +12,9 @@
  *     moments (eq. soe_current_density) or from the central-difference curl of B;
  *   - streaming of both sets along their lattice velocities.
  * Relaxation rates follow the paper: 1/omega = 3 nu + 1/2, 1/omega_B = 4 eta + 1/2.
+ * Variants selected in flame_params: the BGK fluid collision (S = omega I) and the
+ * electron-MHD magnetic equilibrium (Sec. 6). Diagnostics: FP64 reductions, shell energy and
+ * dissipation spectra, and the energy transfer terms of the scale-by-scale budget (Sec. 4.4).
  *
  * Conventions shared by every entry point
  *   - Node index: cell = (z * ny + y) * nx + x.

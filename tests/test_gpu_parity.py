@@ -302,6 +302,23 @@ def test_spectral_diagnostics_on_degenerate_grids(shape):
     s.close()
 
 
+def test_diagnostic_argument_errors():
+    """Host-side refusals of the spectral diagnostics: no kernel is launched by these calls."""
+    from paper_2212_11024_amd import _lib as L
+    s = gpu_solver(Case(8, 6, 5, jmode="moment"), "f64", "aa")
+    import ctypes
+    buf = (ctypes.c_double * 8)()
+    lib = L.load()
+    assert lib.flame_dissipation_spectrum(s.ctx, 2, 8, buf) == L.FLAME_E_INVAL
+    assert lib.flame_dissipation_spectrum(s.ctx, 0, 0, buf) == L.FLAME_E_INVAL
+    assert lib.flame_dissipation_spectrum(s.ctx, 0, 8, None) == L.FLAME_E_INVAL
+    assert lib.flame_energy_transfer(s.ctx, 0, buf, buf, buf) == L.FLAME_E_INVAL
+    assert lib.flame_energy_transfer(s.ctx, 5000, buf, buf, buf) == L.FLAME_E_INVAL
+    assert lib.flame_energy_transfer(s.ctx, 8, buf, None, buf) == L.FLAME_E_INVAL
+    assert lib.flame_energy_transfer(None, 8, buf, buf, buf) == L.FLAME_E_INVAL
+    s.close()
+
+
 def test_nonfinite_detection():
     case = CASES["ragged_moment"]
     s = gpu_solver(case, "f32", "aa")
