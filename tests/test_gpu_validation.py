@@ -3,9 +3,12 @@ errors (eqs. dispersion_error, dissipation_error_new, viscosity_error; oracle/va
 the exact circularly polarised Hall wave (Sec. 4.1; oracle/analytic.py), measured at a fixed
 node over M = 10 periods, under diffusive scaling from N = 32 nodes per wavelength (b0 = 0.1,
 amplitude 1e-3, d_i = 2, nu = eta = 0.01): k b0, k a and k d_i fixed, nu fixed, time in units of
-the period. A second-order scheme makes all three errors fall as N^-2 (the paper's Figs. of the
-dispersion error, the diffusive scaling and the numerical viscosity); the test fits the slope
-over N = 16..256 on the moment route in FP64 storage and asserts it below -1.8."""
+the period; and under acoustic scaling (Mach number and k d_i fixed, nu proportional to 1/N).
+A second-order scheme makes the errors fall as N^-2 (the paper's Figs. of the dispersion error,
+the acoustic and diffusive scalings of the dissipation error and the numerical viscosity); the
+test fits the slopes over N = 16..256 (diffusive: all three) and 16..128 (acoustic: the
+dissipation error) on the moment route in FP64 storage and asserts them below -1.8. Measured:
+diffusive -2.03 / -2.13 / -2.15; acoustic (eps_r 4.8e-2, 2.8e-3, 1.3e-4, 4.3e-5) steeper than -3."""
 
 import math
 
@@ -22,10 +25,20 @@ pytestmark = pytest.mark.gpu
 M = 10
 
 
-def wave_errors(N, branch=+1, nu=0.01):
+def wave_errors(N, branch=+1, scaling="diffusive"):
+    """(eps_phi, eps_r, eps_nu) of the wave at N nodes per wavelength. Diffusive scaling keeps
+    nu and k a, k b0, k d_i fixed; acoustic scaling keeps the lattice velocities a, b0 (the Mach
+    number) and k d_i fixed with nu proportional to 1 / N (a fixed Reynolds number). Acoustic
+    scaling converges to the weakly compressible equations, which differ from the incompressible
+    exact wave by O(Ma^2): it runs at an Alfven Mach number b0 / c_s = 0.017 (b0 = 0.01,
+    amplitude 1e-4, nu = 0.001 at N = 32), in the range of the paper's validation runs, so that
+    floor stays below the errors over N = 16..128."""
     from paper_2212_11024_amd.solver import Solver
     s_ = N / 32
-    amp, b0, d_i = 1e-3 / s_, 0.1 / s_, 2.0 * s_
+    if scaling == "diffusive":
+        amp, b0, d_i, nu = 1e-3 / s_, 0.1 / s_, 2.0 * s_, 0.01
+    else:
+        amp, b0, d_i, nu = 1e-4, 0.01, 2.0 * s_, 0.001 / s_
     k = 2 * math.pi / N
     w = analytic.frequency(d_i, k, b0, branch)
     period = 2 * math.pi / abs(w)
@@ -49,15 +62,21 @@ def wave_errors(N, branch=+1, nu=0.01):
             V.viscosity_error(t, ux, k, nu, M))
 
 
-def test_wave_errors_converge_at_second_order():
-    Ns = [16, 32, 64, 128, 256]
+@pytest.mark.parametrize("scaling", ["diffusive", "acoustic"])
+def test_wave_errors_converge_at_second_order(scaling):
+    Ns = [16, 32, 64, 128, 256] if scaling == "diffusive" else [16, 32, 64, 128]
     errs = []
     for N in Ns:
-        e = wave_errors(N)
-        print(f"[validation] N = {N}: eps_phi {e[0]:.3e}  eps_r {e[1]:.3e}  eps_nu {e[2]:.3e}", flush=True)
+        e = wave_errors(N, scaling=scaling)
+        print(f"[validation] {scaling} N = {N}: eps_phi {e[0]:.3e}  eps_r {e[1]:.3e}  eps_nu {e[2]:.3e}",
+              flush=True)
         errs.append(e)
     errs = np.abs(np.array(errs))
-    for j, name in enumerate(("eps_phi", "eps_r", "eps_nu")):
+    # the paper shows the acoustic scaling for the dissipation error; there the dispersion and
+    # viscosity errors are already near 1e-4 at N = 32 and change sign, so only eps_r is fitted
+    names = ("eps_phi", "eps_r", "eps_nu") if scaling == "diffusive" else ("eps_r",)
+    for name in names:
+        j = ("eps_phi", "eps_r", "eps_nu").index(name)
         slope = np.polyfit(np.log(Ns), np.log(errs[:, j]), 1)[0]
         print(f"[validation] {name}: fitted slope {slope:.3f}", flush=True)
         assert slope < -1.8, (name, errs[:, j], slope)
