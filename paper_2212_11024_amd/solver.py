@@ -149,6 +149,25 @@ class Solver:
         return torch.tensor(L.flame_dissipation_spectrum(self.ctx, {"u": 0, "B": 1}.get(field, field), nshells),
                             dtype=torch.float64)
 
+    def turbulence(self, nshells=None):
+        """Mean-flow summary of the paper's turbulence runs (Sec. 4.4), from the GPU reductions and
+        shell spectra: E_kin, E_mag, the dissipation rate eps = nu <|grad u|^2> + eta <|grad B|^2>
+        (sum of the dissipation spectra), u_rms = <|u|^2>^(1/2), the integral scale
+        L = n sum_s E_u(s) / s / sum_s E_u(s) in cells (box of n cells taken as 2 pi; n the
+        largest axis) and Re = u_rms L / nu."""
+        nshells = nshells or max(self.shape) // 2 + 1
+        red = self.reduce(allow_nonfinite=True)
+        nu = float(self.params.nu)
+        eta = float(self.params.eta)
+        eps = nu * float(self.dissipation_spectrum("u", nshells).sum()) \
+            + eta * float(self.dissipation_spectrum("B", nshells).sum())
+        eu = self.spectrum("u", nshells)[1:]
+        shells = torch.arange(1, nshells, dtype=torch.float64)
+        scale = max(self.shape) * float((eu / shells).sum() / eu.sum()) if float(eu.sum()) > 0 else 0.0
+        u_rms = (2.0 * float(red[0])) ** 0.5
+        return {"E_kin": float(red[0]), "E_mag": float(red[1]), "eps": eps, "u_rms": u_rms,
+                "integral_scale": scale, "Re": u_rms * scale / nu}
+
     def energy_transfer(self, nshells):
         """(T_adv, T_lor, T_ind) per shell, float64 (3, nshells): the summands of the flux
         S_MHD(k) = sum_{s < k} (T_adv + T_lor + T_ind) of the scale-by-scale energy budget."""

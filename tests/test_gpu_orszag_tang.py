@@ -72,6 +72,32 @@ def ot_run(n, storage, re0, eps_h, tau_end, samples, log=None):
     return {"nu": nu, "tau0": tau0, "every": every}, rows
 
 
+def test_turbulence_summary_matches_its_parts():
+    """Solver.turbulence against the same quantities assembled from the reductions and spectra."""
+    from paper_2212_11024_amd.solver import Solver
+    n = 32
+    u0 = MA / math.sqrt(3.0)
+    fu, fb = synthetic.orszag_tang(u0, 0.8 * u0)
+    u, gu = synthetic.evaluate(fu, (n, n, n), "cuda")
+    b, gb = synthetic.evaluate(fb, (n, n, n), "cuda")
+    s = Solver(n, n, n, 0.01, 0.02, 0.5, (0.0, 0.0, 0.0), "f64", "moment", "aa", u, b, gu, gb)
+    s.step(50)
+    t = s.turbulence()
+    ns = n // 2 + 1
+    red = s.reduce()
+    eps = 0.01 * float(s.dissipation_spectrum("u", ns).sum()) + 0.02 * float(s.dissipation_spectrum("B", ns).sum())
+    eu = s.spectrum("u", ns)[1:]
+    scale = n * float((eu / torch.arange(1, ns, dtype=torch.float64)).sum() / eu.sum())
+    assert t["E_kin"] == float(red[0]) and t["E_mag"] == float(red[1])
+    assert abs(t["eps"] / eps - 1) < 1e-12 and abs(t["integral_scale"] / scale - 1) < 1e-12
+    assert abs(t["Re"] - math.sqrt(2 * float(red[0])) * scale / 0.01) < 1e-9 * t["Re"]
+    # the Orszag-Tang velocity lives in shell 1 at t = 0: L is the box
+    s0 = Solver(n, n, n, 0.01, 0.02, 0.5, (0.0, 0.0, 0.0), "f64", "moment", "aa", u, b, gu, gb)
+    assert abs(s0.turbulence()["integral_scale"] - n) < 1e-9 * n
+    s.close()
+    s0.close()
+
+
 def budget(rows):
     """(t / tau0, missing energy E(0) - E(t) - int_0^t eps dt, int_0^t eps dt) at every sample
     after the first, with the trapezoid rule between samples."""
