@@ -333,9 +333,10 @@ def test_nonfinite_detection():
         s.reduce()
 
 
-def test_fp16_storage_tracks_fp32():
-    case = Case(12, 10, 9, jmode="stencil", seed=4)
-    _print_case("f16", steps=50)
+@pytest.mark.parametrize("model", [{}, {"collision": "bgk"}, {"magnetic": "emhd", "jmode": "moment"}])
+def test_fp16_storage_tracks_fp32(model):
+    case = Case(12, 10, 9, **{"jmode": "stencil", "seed": 4, **model})
+    _print_case("f16", steps=50, **model)
     ref = extended_run(case, 50)
     a = gpu_solver(case, "f16", "aa")
     a.step(50)
