@@ -28,6 +28,7 @@ Re = 1122 at the peak (the paper's comparison run: about 1600) at t = 2.6 tau0."
 import math
 import os
 
+import numpy as np
 import pytest
 import torch
 
@@ -38,7 +39,7 @@ pytestmark = pytest.mark.gpu
 MA = 0.025
 
 
-def ot_run(n, storage, re0, eps_h, tau_end, samples, log=None):
+def ot_run(n, storage, re0, eps_h, tau_end, samples, log=None, spectra=None):
     """Run the Orszag-Tang vortex on n^3 to tau_end reference times; (params, rows) with rows of
     (step, t / tau0, E, eps, E_kin, E_mag, <|J|^2>, non-finite nodes, Re). Re = u_rms L / nu with
     u_rms = <|u|^2>^(1/2) and the integral scale L = n sum_s E_u(s) / s / sum_s E_u(s) in cells
@@ -64,6 +65,8 @@ def ot_run(n, storage, re0, eps_h, tau_end, samples, log=None):
         re = math.sqrt(2.0 * float(red[0])) * scale / nu
         rows.append((i * every, i * every / tau0, float(red[0] + red[1]), eps, float(red[0]), float(red[1]),
                      float(red[3]), int(red[8]), re))
+        if spectra is not None:
+            spectra.append((eu.numpy().copy(), s.spectrum("B", ns)[1:].numpy().copy()))
         if log:
             log(rows[-1])
         if i < samples:
@@ -142,13 +145,34 @@ def test_orszag_tang_512_to_dissipation_peak():
         print(f"[orszag-tang 512] step {r[0]} t/tau0 {r[1]:.3f} E {r[2]:.6e} eps {r[3]:.6e} E_kin {r[4]:.6e} "
               f"E_mag {r[5]:.6e} <J^2> {r[6]:.6e} bad {r[7]} Re {r[8]:.0f}", flush=True)
 
-    prm, rows = ot_run(n, "f64", 3200.0, 0.0, 3.0, 60, log)
+    spec = {"f64": [], "f32": []}
+    prm, rows = ot_run(n, "f64", 3200.0, 0.0, 3.0, 60, log, spec["f64"])
     assert all(r[7] == 0 for r in rows)
-    peak = max(rows, key=lambda r: r[3])
+    ip = max(range(len(rows)), key=lambda i: rows[i][3])
+    peak = rows[ip]
     print(f"[orszag-tang 512] nu {prm['nu']:.4e} tau0 {prm['tau0']:.1f} steps; dissipation peak at "
           f"t/tau0 = {peak[1]:.3f}, eps = {peak[3]:.4e}, Re = {peak[8]:.0f}", flush=True)
     check_budget(rows, "orszag-tang 512")
     assert 0 < peak[1] < 3.0 - 1e-9                      # the peak lies inside the run
+    # shell spectra at the peak, normalised by their totals (the paper's comparison at the peak)
+    k = np.arange(1, len(spec["f64"][ip][0]) + 1)
+    for name, e in (("E_u", spec["f64"][ip][0]), ("E_B", spec["f64"][ip][1])):
+        en = e / e.sum()
+        fit = (k >= 4) & (k <= 24)
+        slope = np.polyfit(np.log(k[fit]), np.log(en[fit]), 1)[0]
+        print(f"[orszag-tang 512] {name}(k) / E at the peak, k = 1..32: "
+              + " ".join(f"{x:.3e}" for x in en[:32]) + f"; fitted slope over k = 4..24: {slope:.2f}", flush=True)
+    # the same run with FP32 storage: energies and the spectra at the FP64 peak
+    prm32, rows32 = ot_run(n, "f32", 3200.0, 0.0, 3.0, 60,
+                           lambda r: print(f"[orszag-tang 512 FP32] step {r[0]} E {r[2]:.6e} eps {r[3]:.6e}",
+                                           flush=True), spec["f32"])
+    assert all(r[7] == 0 for r in rows32)
+    de = max(abs(a[2] - b[2]) / b[2] for a, b in zip(rows32, rows))
+    dps = max(abs(a[3] - b[3]) / b[3] for a, b in zip(rows32, rows))
+    su = np.abs(spec["f32"][ip][0][:8] / spec["f64"][ip][0][:8] - 1).max()
+    sb = np.abs(spec["f32"][ip][1][:8] / spec["f64"][ip][1][:8] - 1).max()
+    print(f"[orszag-tang 512] FP32 vs FP64 over the run: energy {de:.2e}, dissipation {dps:.2e} (max relative); "
+          f"shells 1..8 at the peak: E_u {su:.2e}, E_B {sb:.2e}", flush=True)
 
 
 def test_scale_by_scale_budget_64():
