@@ -221,3 +221,34 @@ def test_scale_by_scale_budget_64():
                 worst = max(worst, miss / big)
     print(f"[orszag-tang]   band budget: largest residual from 0.5 tau0 on {worst:.4f} of the largest term",
           flush=True)
+
+
+@pytest.mark.skipif(os.environ.get("FLAME_LARGE") != "1", reason="opt-in 256^3 Hall study (FLAME_LARGE=1)")
+def test_hall_parameter_changes_the_turbulence_256():
+    """The Hall-MHD trends the paper reports for its Orszag-Tang runs (Sec. 5), at 256^3 (FP64,
+    Ma = 0.025, Re0 = 1600, about 600-700 at the peak) for d_i = 0, 2, 4, 8 cells: a larger Hall
+    parameter makes the turbulence develop faster (earlier dissipation peak), and at the peak the
+    sub-ion scales become magnetically dominated with a shallower magnetic spectrum (energy held
+    beyond k_H = n / (2 pi d_i) instead of the MHD run's steep dissipation range). Measured: peak
+    at 2.46 / 2.46 / 2.39 / 2.17 tau0; E_B / E_u over shells k > 20 of 2.2 / 2.2 / 2.8 / 5.8;
+    magnetic slope over k = 20..60 of -6.9 / -6.4 / -5.5 / -4.7."""
+    n = 256
+    res = []
+    for d_i in (0.0, 2.0, 4.0, 8.0):
+        spec = []
+        print(f"[orszag-tang hall] 256^3 FP64, d_i = {d_i}", flush=True)
+        prm, rows = ot_run(n, "f64", 1600.0, d_i / n, 3.5, 50,
+                           lambda r: print(f"[orszag-tang hall] step {r[0]} eps {r[3]:.4e}", flush=True), spec)
+        assert all(r[7] == 0 for r in rows)
+        ip = max(range(len(rows)), key=lambda i: rows[i][3])
+        eu, eb = spec[ip]
+        k = np.arange(1, len(eu) + 1)
+        m = (k >= 20) & (k <= 60)
+        res.append((rows[ip][1], float(eb[k > 20].sum() / eu[k > 20].sum()),
+                    float(np.polyfit(np.log(k[m]), np.log(eb[m]), 1)[0])))
+        print(f"[orszag-tang hall] d_i = {d_i}: peak at {res[-1][0]:.3f} tau0, E_B/E_u (k > 20) {res[-1][1]:.2f}, "
+              f"magnetic slope (k = 20..60) {res[-1][2]:.2f}", flush=True)
+    peaks, ratio, slope = zip(*res)
+    assert peaks[3] < 0.95 * peaks[0]
+    assert all(a <= b for a, b in zip(ratio, ratio[1:])) and ratio[3] > 2 * ratio[0]
+    assert all(a < b for a, b in zip(slope, slope[1:]))
