@@ -181,16 +181,21 @@ flame_status flame_dissipation_spectrum(flame_ctx* c, int32_t field, int32_t nsh
  * per shell s = round(|k|), into host arrays of nshells each:
  *   t_adv[s] =  sum Re[u_hat* . F(U . grad U)],   t_lor[s] = -sum Re[u_hat* . F(J x B)],
  *   t_ind[s] = -sum Re[B_hat* . F(curl(U x B))],
+ * and, when t_hall is not NULL, the Hall term of the induction equation, which the paper's flux
+ * leaves out: t_hall[s] = +d_i sum Re[B_hat* . F(curl(J x B))] (it sums to zero over all shells
+ * for J = curl B: the Hall term moves energy between scales without changing its total),
  * with F = DFT / ncell, U and B the node fields and J the current of the context's route (from
  * the magnetic moments, or the curl stencil). The flux across k is
  * S_MHD(k) = sum_{s < k} (t_adv + t_lor + t_ind); for incompressible MHD without Hall and pressure
- * terms, d/dt sum_{s < k} E(s) = -S_MHD(k) - D(k) with D from flame_dissipation_spectrum.
+ * terms, d/dt sum_{s < k} E(s) = -S_MHD(k) - D(k) with D from flame_dissipation_spectrum (with the
+ * Hall term, -sum_{s < k} t_hall is added to the right-hand side).
  * Derivatives are spectral, q_a = 2 pi k_a / n_a, and 0 on the Nyquist index of an even axis;
  * products are formed node by node. FP64 throughout (hipFFT). Allocates 11 node fields and 7
  * half spectra of device memory for the call (19 GB at 512^3) and frees them before returning;
- * FLAME_E_NOMEM if that fails. FLAME_E_INVAL for nshells outside 1..4096 or a NULL output.
- * Synchronises. */
-flame_status flame_energy_transfer(flame_ctx* c, int32_t nshells, double* t_adv, double* t_lor, double* t_ind);
+ * FLAME_E_NOMEM if that fails. FLAME_E_INVAL for nshells outside 1..4096 or a NULL t_adv, t_lor
+ * or t_ind. Synchronises. */
+flame_status flame_energy_transfer(flame_ctx* c, int32_t nshells, double* t_adv, double* t_lor, double* t_ind,
+                                   double* t_hall);
 
 /* Copy the state in canonical order to / from device double dst/src [48 * ncell].
  * deviations = 0: full population values; deviations = 1: departures from the rest state of

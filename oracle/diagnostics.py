@@ -21,7 +21,10 @@ Energy transfer (the summands of the flux S_MHD(k) in Sec. 4.4, per shell s):
   T_adv(s) = sum Re[u_hat* . F(U . grad U)],  T_lor(s) = -sum Re[u_hat* . F(J x B)],
   T_ind(s) = -sum Re[B_hat* . F(curl(U x B))],
 so that S_MHD(k) = sum_{s < k} (T_adv + T_lor + T_ind) and, for incompressible MHD without the
-Hall and pressure terms, d/dt sum_{s < k} E(s) = -S_MHD(k) - D(k). Derivatives are spectral with
+Hall and pressure terms, d/dt sum_{s < k} E(s) = -S_MHD(k) - D(k). The Hall term of the induction
+equation, -alpha_H curl(J x B), which the paper's flux leaves out, transfers
+T_hall(s) = +alpha_H sum Re[B_hat* . F(curl(J x B))]; it conserves the energy (its sum over all
+shells is alpha_H <J . (J x B)> = 0 for J = curl B). Derivatives are spectral with
 q_a = 2 pi k_a / n_a, except that q_a = 0 on the Nyquist index of an even axis (that mode's
 derivative is not a real field). Products are formed node by node on the grid.
 """
@@ -104,8 +107,9 @@ def derivative_wavenumbers(n):
     return q
 
 
-def energy_transfer(U, B, J, nshells):
-    """(T_adv, T_lor, T_ind), each (nshells,), of (3, nz, ny, nx) real fields U, B and J."""
+def energy_transfer(U, B, J, nshells, d_i=None):
+    """(T_adv, T_lor, T_ind), each (nshells,), of (3, nz, ny, nx) real fields U, B and J; with
+    d_i (alpha_H) given, T_hall is appended."""
     U, B, J = [x.detach().cpu().numpy() if torch.is_tensor(x) else np.asarray(x) for x in (U, B, J)]
     nz, ny, nx = U.shape[1:]
     ncell = U[0].size
@@ -126,12 +130,16 @@ def energy_transfer(U, B, J, nshells):
     Wh = [hat(W[b]) for b in range(3)]
     t_adv = sum(binned(np.real(np.conj(Uh[b]) * hat(adv[b]))) for b in range(3))
     t_lor = -sum(binned(np.real(np.conj(Uh[b]) * hat(lor[b]))) for b in range(3))
-    t_ind = np.zeros(nshells)
-    for b in range(3):
+    def curl_hat(Vh, b):
         c, d = (b + 1) % 3, (b + 2) % 3
-        curl_b = 1j * (Q[c] * Wh[d] - Q[d] * Wh[c])
-        t_ind -= binned(np.real(np.conj(Bh[b]) * curl_b))
-    return t_adv, t_lor, t_ind
+        return 1j * (Q[c] * Vh[d] - Q[d] * Vh[c])
+
+    t_ind = -sum(binned(np.real(np.conj(Bh[b]) * curl_hat(Wh, b))) for b in range(3))
+    if d_i is None:
+        return t_adv, t_lor, t_ind
+    Lh = [hat(lor[b]) for b in range(3)]
+    t_hall = d_i * sum(binned(np.real(np.conj(Bh[b]) * curl_hat(Lh, b))) for b in range(3))
+    return t_adv, t_lor, t_ind, t_hall
 
 
 def max_shell(shape):

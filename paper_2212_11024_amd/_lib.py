@@ -53,7 +53,7 @@ _SIGNATURES = {
     "flame_spectrum": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
     "flame_dissipation_spectrum": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32,
                                                     ctypes.POINTER(ctypes.c_double)]),
-    "flame_energy_transfer": (ctypes.c_int32, [_P, ctypes.c_int32] + [ctypes.POINTER(ctypes.c_double)] * 3),
+    "flame_energy_transfer": (ctypes.c_int32, [_P, ctypes.c_int32] + [ctypes.POINTER(ctypes.c_double)] * 4),
     "flame_get_populations": (ctypes.c_int32, [_P, _P, ctypes.c_int32]),
     "flame_set_populations": (ctypes.c_int32, [_P, _P, ctypes.c_int32]),
     "flame_gather": (ctypes.c_int32, [_P, _P, ctypes.c_int64, _P, ctypes.c_int32]),
@@ -155,9 +155,9 @@ def flame_dissipation_spectrum(ctx: int, field: int, nshells: int):
     return list(out)
 
 
-def flame_energy_transfer(ctx: int, nshells: int):
-    out = [(ctypes.c_double * nshells)() for _ in range(3)]
-    _check(load().flame_energy_transfer(ctx, nshells, *out), ctx)
+def flame_energy_transfer(ctx: int, nshells: int, hall: bool = False):
+    out = [(ctypes.c_double * nshells)() for _ in range(4 if hall else 3)]
+    _check(load().flame_energy_transfer(ctx, nshells, *out, *([] if hall else [None])), ctx)
     return [list(o) for o in out]
 
 

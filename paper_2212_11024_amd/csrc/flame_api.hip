@@ -529,7 +529,7 @@ __global__ __launch_bounds__(256) void cross_component_kernel(const double* P, c
 
 // Per-block shell sums of one transfer summand over the half spectrum (entries with
 // 0 < kx < nx - kx stand for their mirror too, whose summand is equal). kind 0:
-// sign Re[conj(X) Y]; kind 1: -Re[i Y (conj(B_hat) x q)_comp] = -Re[conj(B_hat) . (i q x Y e_comp)]
+// sign Re[conj(X) Y]; kind 1: -sign Re[i Y (conj(B_hat) x q)_comp] = -sign Re[conj(B_hat) . (i q x Y e_comp)]
 // summed over comp by the caller, with B_hat the three transforms in Bh. Adds into partials
 // unless first is set.
 __global__ __launch_bounds__(kSpecThreads) void transfer_bin_kernel(int kind, const hipfftDoubleComplex* X,
@@ -562,7 +562,7 @@ __global__ __launch_bounds__(kSpecThreads) void transfer_bin_kernel(int kind, co
       const double zr = bc.x * q[d] - bd.x * q[c];
       const double zi = -bc.y * q[d] + bd.y * q[c];
       // -Re[i y z] = Im[y z]
-      v = y.x * zi + y.y * zr;
+      v = sign * (y.x * zi + y.y * zr);
     }
     const double mult = (kx == 0 || 2 * kx == nx) ? 1.0 : 2.0;
     atomicAdd(&bins[shell], mult * v * norm2);
@@ -1007,7 +1007,8 @@ struct TransferScratch {
   }
 };
 
-flame_status energy_transfer(flame_ctx* c, int32_t nshells, double* t_adv, double* t_lor, double* t_ind) {
+flame_status energy_transfer(flame_ctx* c, int32_t nshells, double* t_adv, double* t_lor, double* t_ind,
+                             double* t_hall) {
   if (!c) return FLAME_E_INVAL;
   if (nshells < 1 || nshells > kSpecShellsMax) return fail(c, FLAME_E_INVAL, "nshells out of range");
   if (!t_adv || !t_lor || !t_ind) return fail(c, FLAME_E_INVAL, "an output array is NULL");
@@ -1031,7 +1032,7 @@ flame_status energy_transfer(flame_ctx* c, int32_t nshells, double* t_adv, doubl
   TransferScratch w;
   if (hipMalloc(&w.real, sizeof(double) * 11 * n) != hipSuccess ||
       hipMalloc(&w.cplx, sizeof(hipfftDoubleComplex) * 7 * nh) != hipSuccess ||
-      hipMalloc(&w.partials, sizeof(double) * 3 * blocks * nshells) != hipSuccess)
+      hipMalloc(&w.partials, sizeof(double) * 4 * blocks * nshells) != hipSuccess)
     return fail(c, FLAME_E_NOMEM, "energy transfer: device workspace");
   double* U = w.real;
   double* B = w.real + 3 * n;
@@ -1077,10 +1078,11 @@ flame_status energy_transfer(flame_ctx* c, int32_t nshells, double* t_adv, doubl
       }
     }
     ok = ok && forward(adv, spec) && bin(0, 0, Uh + b * nh, b, 1.0, b == 0);
-    // Lorentz force (J x B)_b
+    // Lorentz force (J x B)_b; the Hall term takes the same transform against conj(B_hat) x q
     if (ok) {
       hipLaunchKernelGGL(cross_component_kernel, dim3(gn), dim3(256), 0, c->stream, J, B, b, n, work);
       ok = hipGetLastError() == hipSuccess && forward(work, spec) && bin(0, 1, Uh + b * nh, b, -1.0, b == 0);
+      if (ok && t_hall) ok = bin(1, 3, nullptr, b, -c->p.d_i, b == 0);
     }
     // induction: (U x B)_b, binned against conj(B_hat) x q
     if (ok) {
@@ -1088,7 +1090,8 @@ flame_status energy_transfer(flame_ctx* c, int32_t nshells, double* t_adv, doubl
       ok = hipGetLastError() == hipSuccess && forward(work, spec) && bin(1, 2, nullptr, b, 1.0, b == 0);
     }
   }
-  std::vector<double> host(static_cast<size_t>(3) * blocks * nshells);
+  const int terms = t_hall ? 4 : 3;
+  std::vector<double> host(static_cast<size_t>(terms) * blocks * nshells);
   if (ok) ok = hipMemcpyAsync(host.data(), w.partials, sizeof(double) * host.size(), hipMemcpyDeviceToHost,
                               c->stream) == hipSuccess;
   if (ok) ok = hipStreamSynchronize(c->stream) == hipSuccess;
@@ -1097,8 +1100,8 @@ flame_status energy_transfer(flame_ctx* c, int32_t nshells, double* t_adv, doubl
     return fail(c, FLAME_E_HIP, std::string("energy transfer: a transform, copy or kernel launch failed (") +
                                     hipGetErrorString(last) + ")");
   }
-  double* outs[3] = {t_adv, t_lor, t_ind};
-  for (int t = 0; t < 3; ++t) {
+  double* outs[4] = {t_adv, t_lor, t_ind, t_hall};
+  for (int t = 0; t < terms; ++t) {
     for (int s = 0; s < nshells; ++s) outs[t][s] = 0.0;
     for (int blk = 0; blk < blocks; ++blk)
       for (int s = 0; s < nshells; ++s) outs[t][s] += host[(static_cast<size_t>(t) * blocks + blk) * nshells + s];
@@ -1110,8 +1113,9 @@ flame_status energy_transfer(flame_ctx* c, int32_t nshells, double* t_adv, doubl
 
 extern "C" {
 
-flame_status flame_energy_transfer(flame_ctx* c, int32_t nshells, double* t_adv, double* t_lor, double* t_ind) {
-  return energy_transfer(c, nshells, t_adv, t_lor, t_ind);
+flame_status flame_energy_transfer(flame_ctx* c, int32_t nshells, double* t_adv, double* t_lor, double* t_ind,
+                                   double* t_hall) {
+  return energy_transfer(c, nshells, t_adv, t_lor, t_ind, t_hall);
 }
 
 flame_status flame_get_populations(flame_ctx* c, double* dst, int32_t deviations) {

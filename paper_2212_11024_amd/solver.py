@@ -168,10 +168,11 @@ class Solver:
         return {"E_kin": float(red[0]), "E_mag": float(red[1]), "eps": eps, "u_rms": u_rms,
                 "integral_scale": scale, "Re": u_rms * scale / nu}
 
-    def energy_transfer(self, nshells):
+    def energy_transfer(self, nshells, hall=False):
         """(T_adv, T_lor, T_ind) per shell, float64 (3, nshells): the summands of the flux
-        S_MHD(k) = sum_{s < k} (T_adv + T_lor + T_ind) of the scale-by-scale energy budget."""
-        return torch.tensor(L.flame_energy_transfer(self.ctx, nshells), dtype=torch.float64)
+        S_MHD(k) = sum_{s < k} (T_adv + T_lor + T_ind) of the scale-by-scale energy budget; with
+        hall=True a fourth row, the Hall term's transfer T_hall."""
+        return torch.tensor(L.flame_energy_transfer(self.ctx, nshells, hall), dtype=torch.float64)
 
     # -- canonical state
     def get_populations(self, deviations=False):

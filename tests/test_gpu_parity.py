@@ -198,11 +198,13 @@ def test_energy_transfer_vs_oracle(shape, jmode):
     s.step(7)
     _, ou, oB, oJ, _ = scheme.fields(st, p)
     ns = diagnostics.max_shell(p.shape)
-    got = s.energy_transfer(ns)
-    ref = torch.tensor(np.stack(diagnostics.energy_transfer(ou, oB, oJ, ns)))
+    got = s.energy_transfer(ns, hall=True)
+    ref = torch.tensor(np.stack(diagnostics.energy_transfer(ou, oB, oJ, ns, d_i=case.d_i)))
     scale = float(ref.abs().max())
-    assert scale > 0
+    assert scale > 0 and float(ref[3].abs().max()) > 0
     assert float((got - ref).abs().max()) < 1e-11 * scale
+    # without the Hall row the three terms are the same (up to the order of the shell sums)
+    assert float((s.energy_transfer(ns) - got[:3]).abs().max()) < 1e-13 * scale
 
 
 def test_exact_wave_on_gpu_matches_oracle():
@@ -312,10 +314,10 @@ def test_diagnostic_argument_errors():
     assert lib.flame_dissipation_spectrum(s.ctx, 2, 8, buf) == L.FLAME_E_INVAL
     assert lib.flame_dissipation_spectrum(s.ctx, 0, 0, buf) == L.FLAME_E_INVAL
     assert lib.flame_dissipation_spectrum(s.ctx, 0, 8, None) == L.FLAME_E_INVAL
-    assert lib.flame_energy_transfer(s.ctx, 0, buf, buf, buf) == L.FLAME_E_INVAL
-    assert lib.flame_energy_transfer(s.ctx, 5000, buf, buf, buf) == L.FLAME_E_INVAL
-    assert lib.flame_energy_transfer(s.ctx, 8, buf, None, buf) == L.FLAME_E_INVAL
-    assert lib.flame_energy_transfer(None, 8, buf, buf, buf) == L.FLAME_E_INVAL
+    assert lib.flame_energy_transfer(s.ctx, 0, buf, buf, buf, None) == L.FLAME_E_INVAL
+    assert lib.flame_energy_transfer(s.ctx, 5000, buf, buf, buf, buf) == L.FLAME_E_INVAL
+    assert lib.flame_energy_transfer(s.ctx, 8, buf, None, buf, None) == L.FLAME_E_INVAL
+    assert lib.flame_energy_transfer(None, 8, buf, buf, buf, None) == L.FLAME_E_INVAL
     s.close()
 
 

@@ -275,21 +275,24 @@ def _dft_brute(v):
     return np.einsum("az,by,cx,zyx->abc", mats[0], mats[1], mats[2], v) / v.size
 
 
-def _transfer_brute(U, gU, B, gB, J, nshells):
-    """Energy transfer from exact node derivatives (mode sums, product rule) and explicit DFTs,
-    binned by round(|k|) with the signed index written out in a loop."""
-    U, gU, B, gB, J = [x.numpy() for x in (U, gU, B, gB, J)]
+def _transfer_brute(U, gU, B, gB, J, gJ, nshells, d_i):
+    """Energy transfer (with the Hall term) from exact node derivatives (mode sums, product rule)
+    and explicit DFTs, binned by round(|k|) with the signed index written out in a loop."""
+    U, gU, B, gB, J, gJ = [x.numpy() for x in (U, gU, B, gB, J, gJ)]
     adv = np.stack([sum(U[a] * gU[a, b] for a in range(3)) for b in range(3)])
     lor = np.stack([J[1] * B[2] - J[2] * B[1], J[2] * B[0] - J[0] * B[2], J[0] * B[1] - J[1] * B[0]])
     # d_a (U x B) = d_a U x B + U x d_a B, then curl
     dW = np.stack([np.cross(gU[a], B, axis=0) + np.cross(U, gB[a], axis=0) for a in range(3)])
     curlW = np.stack([dW[1, 2] - dW[2, 1], dW[2, 0] - dW[0, 2], dW[0, 1] - dW[1, 0]])
+    dL = np.stack([np.cross(gJ[a], B, axis=0) + np.cross(J, gB[a], axis=0) for a in range(3)])
+    curlL = np.stack([dL[1, 2] - dL[2, 1], dL[2, 0] - dL[0, 2], dL[0, 1] - dL[1, 0]])
     F = lambda v: _dft_brute(v)  # noqa: E731
     ta = sum(np.real(np.conj(F(U[b])) * F(adv[b])) for b in range(3))
     tl = -sum(np.real(np.conj(F(U[b])) * F(lor[b])) for b in range(3))
     ti = -sum(np.real(np.conj(F(B[b])) * F(curlW[b])) for b in range(3))
+    th = d_i * sum(np.real(np.conj(F(B[b])) * F(curlL[b])) for b in range(3))
     nz, ny, nx = U.shape[1:]
-    out = np.zeros((3, nshells))
+    out = np.zeros((4, nshells))
     signed = lambda k, n: k if k <= (n - 1) // 2 else k - n  # noqa: E731
     for kz in range(nz):
         for ky in range(ny):
@@ -297,7 +300,7 @@ def _transfer_brute(U, gU, B, gB, J, nshells):
                 m = (signed(kx, nx), signed(ky, ny), signed(kz, nz))
                 s = int(math.floor(math.sqrt(m[0] ** 2 + m[1] ** 2 + m[2] ** 2) + 0.5))
                 if s < nshells:
-                    out[:, s] += (ta[kz, ky, kx], tl[kz, ky, kx], ti[kz, ky, kx])
+                    out[:, s] += (ta[kz, ky, kx], tl[kz, ky, kx], ti[kz, ky, kx], th[kz, ky, kx])
     return out
 
 
@@ -308,10 +311,10 @@ def test_energy_transfer_matches_brute_force():
     shape = (5, 6, 7)
     U, gU = synthetic.evaluate(synthetic.shell_field(41, 1, 1, 0.3), shape)
     B, gB = synthetic.evaluate(synthetic.shell_field(42, 1, 1, 0.2), shape)
-    J, _ = synthetic.evaluate(synthetic.shell_field(43, 1, 1, 0.1), shape, gradient=False)
+    J, gJ = synthetic.evaluate(synthetic.shell_field(43, 1, 1, 0.1), shape)
     ns = diagnostics.max_shell(shape[::-1])
-    got = np.stack(diagnostics.energy_transfer(U, B, J, ns))
-    ref = _transfer_brute(U, gU, B, gB, J, ns)
+    got = np.stack(diagnostics.energy_transfer(U, B, J, ns, d_i=1.7))
+    ref = _transfer_brute(U, gU, B, gB, J, gJ, ns, 1.7)
     scale = np.abs(ref).max()
     assert scale > 1e-4
     assert np.abs(got - ref).max() < 1e-13 * scale
@@ -327,6 +330,14 @@ def test_energy_transfer_conserves_energy():
     J = torch.stack([gB[1, 2] - gB[2, 1], gB[2, 0] - gB[0, 2], gB[0, 1] - gB[1, 0]])
     ta, tl, ti = diagnostics.energy_transfer(U, B, J, diagnostics.max_shell(shape[::-1]))
     assert np.abs(tl).sum() > 1e-5 and abs(tl.sum() + ti.sum()) < 1e-14 * np.abs(tl).sum()
+    # the Hall term conserves the energy on its own: alpha_H <J . (J x B)> = 0 for J = curl B;
+    # B in shells 1 and 2 (a field in one shell only has nothing to move between shells), on a
+    # grid where the products of |k_a| <= 2 modes are not aliased
+    shape = (9, 10, 11)
+    B, gB = synthetic.evaluate(synthetic.shell_field(47, 1, 2, 0.2), shape)
+    J = torch.stack([gB[1, 2] - gB[2, 1], gB[2, 0] - gB[0, 2], gB[0, 1] - gB[1, 0]])
+    *_, th = diagnostics.energy_transfer(B, B, J, diagnostics.max_shell(shape[::-1]), d_i=2.5)
+    assert np.abs(th).sum() > 1e-6 and abs(th.sum()) < 1e-14 * np.abs(th).sum()
     n = 9
     U, _ = synthetic.evaluate(synthetic.shell_field(46, 1, 2, 0.3), (n, n, n))
     ta, _, _ = diagnostics.energy_transfer(U, U, U, diagnostics.max_shell((n, n, n)))
