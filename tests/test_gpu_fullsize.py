@@ -1,5 +1,5 @@
 """Parity at the benchmark's full size and launch configuration (512^3 forced Hall-MHD
-turbulence, FP32 deviation storage, AA layout), on sampled nodes: the pre-step populations
+turbulence, AA layout, FP32 and FP64 deviation storage), on sampled nodes: the pre-step populations
 of the 5^3 neighbourhood of each sampled node are read back, the oracle steps that periodic
 5^3 box once (the centre depends only on nodes within two cells, for either J route), and
 the centre is compared with the GPU's post-step populations. Checked after an odd and an
@@ -29,14 +29,24 @@ def _neighbourhood(centres):
     return np.concatenate(out)
 
 
-@pytest.mark.parametrize("jmode", ["stencil", "moment"])
-def test_sampled_parity_at_benchmark_size(jmode):
+# relative L2 error over the sampled nodes and the worst single node, per storage: the FP32
+# step rounds its arithmetic and stores to FP32; the FP64 step differs from the oracle by
+# rounding order only
+BARS = {"f32": (1e-5, 1e-4), "f64": (1e-12, 1e-11)}
+
+
+@pytest.mark.parametrize("storage,jmode", [("f32", "stencil"), ("f32", "moment"), ("f64", "moment"),
+                                           ("f64", "stencil")])
+def test_sampled_parity_at_benchmark_size(storage, jmode):
     import bench
-    print(f"[fullsize] {N}^3 f32 {jmode} aa", flush=True)
+    print(f"[fullsize] {N}^3 {storage} {jmode} aa", flush=True)
     fields = bench.workload_fields(N, "cuda")
-    s = bench.make_solver(N, "f32", jmode, "aa", fields=fields)
-    fu32 = fields[4].float().double()
-    fb32 = fields[5].float().double()
+    s = bench.make_solver(N, storage, jmode, "aa", fields=fields)
+    # the forcing as the kernel sees it: stored in the arithmetic type
+    cast = (lambda t: t.float().double()) if storage == "f32" else (lambda t: t.double())
+    fu_k = cast(fields[4])
+    fb_k = cast(fields[5])
+    del fields
     rng = np.random.default_rng(42)
     centres = rng.integers(0, N, size=(NSAMPLE, 3))
     nb = torch.as_tensor(_neighbourhood(centres), device="cuda")
@@ -47,8 +57,8 @@ def test_sampled_parity_at_benchmark_size(jmode):
     for advance in (3, 1):
         s.step(advance)
         pre = s.gather(nb).cpu().view(NSAMPLE, 125, 48)
-        fpre = fu32.flatten(1)[:, nb].cpu().view(3, NSAMPLE, 125)
-        bpre = fb32.flatten(1)[:, nb].cpu().view(3, NSAMPLE, 125)
+        fpre = fu_k.flatten(1)[:, nb].cpu().view(3, NSAMPLE, 125)
+        bpre = fb_k.flatten(1)[:, nb].cpu().view(3, NSAMPLE, 125)
         s.step(1)
         post = s.gather(mid, deviations=True).cpu()
         num = den = 0.0
@@ -66,8 +76,8 @@ def test_sampled_parity_at_benchmark_size(jmode):
             den += w
             worst = max(worst, (d / w) ** 0.5)
         err = (num / den) ** 0.5
-        print(f"[fullsize] {jmode} after {s.steps} steps: sampled relative error {err:.3e}, worst node {worst:.3e}",
-              flush=True)
-        assert err < 1e-5 and worst < 1e-4
+        print(f"[fullsize] {storage} {jmode} after {s.steps} steps: sampled relative error {err:.3e}, "
+              f"worst node {worst:.3e}", flush=True)
+        assert err < BARS[storage][0] and worst < BARS[storage][1]
     red = s.reduce()
     assert red[8] == 0
