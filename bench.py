@@ -39,8 +39,14 @@ HBM_PEAK_GBPS = 8000.0        # MI355X HBM3E peak
 # HBM traffic of the headline kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE passes, calibrated on
 # a plain copy (see the traffic summary named below). Valid only for the kernel source it was
 # measured on: reported as null once the fingerprint of the kernel sources changes.
-TRAFFIC_RECORD = {"fingerprint": "845b728891c4796b", "GB_per_launch": 55.3,
-                  "profile": "profiles/traffic_step_f32_moment_512.md"}
+TRAFFIC_RECORDS = {
+    ("f32", "moment"): {"fingerprint": "845b728891c4796b", "GB_per_launch": 55.3,
+                        "profile": "profiles/traffic_step_f32_moment_512.md"},
+    ("f32", "stencil"): {"fingerprint": "845b728891c4796b", "GB_per_launch": 69.2,
+                         "profile": "profiles/traffic_step_f32_stencil_512.md"},
+    ("f64", "moment"): {"fingerprint": "845b728891c4796b", "GB_per_launch": 110.3,
+                        "profile": "profiles/traffic_step_f64_moment_512.md"},
+}
 
 
 def kernel_fingerprint():
@@ -365,7 +371,9 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--size", type=int, default=512)
     ap.add_argument("--variants", default="all",
-                    help="all | headline | stencil (the FP32 stencil kernel alone) | adjoint (the reverse-mode "
+                    choices=["all", "headline", "stencil", "f64", "adjoint", "orszag-tang"],
+                    help="all | headline | stencil (the FP32 stencil kernel alone) | f64 (the FP64 moment-route "
+                         "step alone) | adjoint (the reverse-mode "
                          "segments alone, printed as one JSON list) | orszag-tang (the paper's own workload "
                          "alone, FP64 and FP32, one JSON list)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -401,7 +409,8 @@ def main(argv=None):
     fields = workload_fields(n, "cuda")
     torch.cuda.synchronize()
     d_i = PHYS["d_i"]
-    variants = [("f32", "stencil", d_i)] if args.variants == "stencil" else [("f32", "moment", d_i)]
+    single = {"stencil": ("f32", "stencil"), "f64": ("f64", "moment")}.get(args.variants, ("f32", "moment"))
+    variants = [(*single, d_i)]
     if args.variants == "all":
         # The headline (first entry) is measured last: in a fresh process the first population
         # buffers obtained were all of the slow physical placement in two of three bench runs,
@@ -448,8 +457,10 @@ def main(argv=None):
             print(f"[bench]   {adj[-1]}", file=sys.stderr, flush=True)
     head = results[0]
     traffic = None
-    if n == 512 and TRAFFIC_RECORD["fingerprint"] and kernel_fingerprint() == TRAFFIC_RECORD["fingerprint"]:
-        traffic = TRAFFIC_RECORD["GB_per_launch"]
+    rec = TRAFFIC_RECORDS.get((head["storage"], head["jmode"]))
+    if (n == 512 and rec and (head["collision"], head["magnetic"]) == ("central", "hall")
+            and kernel_fingerprint() == rec["fingerprint"]):
+        traffic = rec["GB_per_launch"]
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
@@ -465,11 +476,13 @@ def main(argv=None):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": head["storage"],
         "data": "synthetic (seeded Fourier-mode fields)",
-        "config": {"workload": WORKLOAD if n == 512 else WORKLOAD.replace("512^3", f"{n}^3"),
+        "config": {"workload": (WORKLOAD if n == 512 else WORKLOAD.replace("512^3", f"{n}^3")).replace(
+                       "FP32", head["storage"].upper().replace("F", "FP")),
                    "grid": [n, n, n], "nu": PHYS["nu"], "eta": PHYS["eta"], "d_i": PHYS["d_i"],
-                   "j_mode": "moment", "layout": "aa (fluid and magnetic in place)",
+                   "j_mode": head["jmode"],
+                   "layout": "aa (fluid in place; magnetic in place for moment J, two lattices for stencil J)",
                    "forcing": "static, |k| <= 2, rms 1e-5",
                    "placement": f"fastest of up to {args.placement_trials} population buffers over a 3-step "
                                 "probe each (trial timings in the variants' placement_trials_ms)"},
