@@ -164,7 +164,9 @@ flame_status flame_reduce(flame_ctx* c, double* out);
 
 /* Shell energy spectrum of u (field = 0) or B (field = 1) into host e_k[nshells]:
  * E(s) = 1/2 sum_{round(|k|) = s} |v_hat(k)|^2, v_hat = DFT(v) / ncell, k the signed integer
- * wavevector (paper Sec. 4.4 spectra). FP64 FFT (hipFFT) and binning. Synchronises. */
+ * wavevector (paper Sec. 4.4 spectra). FP64 FFT (hipFFT) and binning. Synchronises. The first
+ * call allocates a workspace of one node field and one half spectrum (kept until flame_destroy);
+ * FLAME_E_NOMEM if that fails, and a later call tries again. */
 flame_status flame_spectrum(flame_ctx* c, int32_t field, int32_t nshells, double* e_k);
 
 /* Shell dissipation spectrum of u (field = 0) or B (field = 1) into host d_k[nshells]:

@@ -934,9 +934,17 @@ flame_status shell_spectrum(flame_ctx* c, int32_t field, int32_t nshells, int k2
   if (!e_k) return fail(c, FLAME_E_INVAL, "e_k is NULL");
   const int nx = c->p.nx, ny = c->p.ny, nz = c->p.nz;
   const size_t nh = static_cast<size_t>(nz) * ny * (nx / 2 + 1);
-  if (!c->spec_real) {
-    FLAME_HIP(c, hipMalloc(&c->spec_real, sizeof(double) * c->n));
-    FLAME_HIP(c, hipMalloc(&c->spec_cplx, sizeof(hipfftDoubleComplex) * nh));
+  // each buffer is checked on its own, and a failed allocation leaves its pointer null, so a call
+  // after an out-of-memory failure allocates again instead of launching on a missing buffer
+  if (!c->spec_real && hipMalloc(&c->spec_real, sizeof(double) * c->n) != hipSuccess) {
+    c->spec_real = nullptr;
+    (void)hipGetLastError();  // clear the allocation error so later launch checks do not see it
+    return fail(c, FLAME_E_NOMEM, "spectrum: device workspace");
+  }
+  if (!c->spec_cplx && hipMalloc(&c->spec_cplx, sizeof(hipfftDoubleComplex) * nh) != hipSuccess) {
+    c->spec_cplx = nullptr;
+    (void)hipGetLastError();  // clear the allocation error so later launch checks do not see it
+    return fail(c, FLAME_E_NOMEM, "spectrum: device workspace");
   }
   if (!c->plan_ok) {
     if (hipfftPlan3d(&c->plan, nz, ny, nx, HIPFFT_D2Z) != HIPFFT_SUCCESS)
@@ -945,10 +953,16 @@ flame_status shell_spectrum(flame_ctx* c, int32_t field, int32_t nshells, int k2
     if (hipfftSetStream(c->plan, c->stream) != HIPFFT_SUCCESS) return fail(c, FLAME_E_HIP, "hipfftSetStream failed");
   }
   const int blocks = static_cast<int>(std::min<size_t>(1024, blocks_for(nh, kSpecThreads)));
-  if (c->spec_blocks != blocks || c->spec_nshells < nshells) {
+  if (!c->spec_partials || c->spec_blocks != blocks || c->spec_nshells < nshells) {
     if (c->spec_partials) FLAME_HIP(c, hipFree(c->spec_partials));
     c->spec_partials = nullptr;
-    FLAME_HIP(c, hipMalloc(&c->spec_partials, sizeof(double) * blocks * nshells));
+    c->spec_blocks = 0;
+    c->spec_nshells = 0;
+    if (hipMalloc(&c->spec_partials, sizeof(double) * blocks * nshells) != hipSuccess) {
+      c->spec_partials = nullptr;
+      (void)hipGetLastError();  // clear the allocation error so later launch checks do not see it
+      return fail(c, FLAME_E_NOMEM, "spectrum: device workspace");
+    }
     c->spec_blocks = blocks;
     c->spec_nshells = nshells;
   }
@@ -995,12 +1009,16 @@ flame_status flame_dissipation_spectrum(flame_ctx* c, int32_t field, int32_t nsh
 
 namespace {
 
-// Device buffers of one energy-transfer evaluation, released on every return.
+// Device buffers of one energy-transfer evaluation, released on every return once the work
+// queued on the stream (which may still use them on an error path) has finished.
 struct TransferScratch {
+  hipStream_t stream;
   double* real = nullptr;              // U(3) B(3) J(3), a work field, the advection product
   hipfftDoubleComplex* cplx = nullptr; // u_hat(3) B_hat(3), a work spectrum
-  double* partials = nullptr;          // 3 terms x blocks x nshells
+  double* partials = nullptr;          // 4 terms x blocks x nshells
+  explicit TransferScratch(hipStream_t s) : stream(s) {}
   ~TransferScratch() {
+    (void)hipStreamSynchronize(stream);
     if (real) (void)hipFree(real);
     if (cplx) (void)hipFree(cplx);
     if (partials) (void)hipFree(partials);
@@ -1029,11 +1047,14 @@ flame_status energy_transfer(flame_ctx* c, int32_t nshells, double* t_adv, doubl
       return fail(c, FLAME_E_HIP, "hipfftSetStream failed");
   }
   const int blocks = static_cast<int>(std::min<size_t>(1024, blocks_for(nh, kSpecThreads)));
-  TransferScratch w;
-  if (hipMalloc(&w.real, sizeof(double) * 11 * n) != hipSuccess ||
-      hipMalloc(&w.cplx, sizeof(hipfftDoubleComplex) * 7 * nh) != hipSuccess ||
-      hipMalloc(&w.partials, sizeof(double) * 4 * blocks * nshells) != hipSuccess)
+  TransferScratch w(c->stream);
+  if (hipMalloc(&w.real, sizeof(double) * 11 * n) != hipSuccess) w.real = nullptr;
+  if (w.real && hipMalloc(&w.cplx, sizeof(hipfftDoubleComplex) * 7 * nh) != hipSuccess) w.cplx = nullptr;
+  if (w.cplx && hipMalloc(&w.partials, sizeof(double) * 4 * blocks * nshells) != hipSuccess) w.partials = nullptr;
+  if (!w.partials) {
+    (void)hipGetLastError();  // clear the allocation error so later launch checks do not see it
     return fail(c, FLAME_E_NOMEM, "energy transfer: device workspace");
+  }
   double* U = w.real;
   double* B = w.real + 3 * n;
   double* J = w.real + 6 * n;
