@@ -26,6 +26,18 @@ def declared_functions():
     return sorted(set(re.findall(r"\b(flame_[a-z0-9_]+)\s*\(", text)))
 
 
+def test_header_is_plain_c():
+    """The boundary header compiles as strict C99 (no C++ or torch types in the signatures)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    r = subprocess.run([cc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-fsyntax-only", "-x", "c",
+                        HEADER], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+
+
 def test_header_declares_the_boundary():
     names = declared_functions()
     for required in ("flame_init", "flame_step", "flame_moments", "flame_spectrum", "flame_reduce",
