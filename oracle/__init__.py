@@ -12,7 +12,9 @@ Modules, each following the paper passage named in its header:
   current      J from the moments (3x3 system) or the curl stencil; div B estimate
   scheme       moments, collide, stream, initial state, node fields
   analytic     exact damped Hall-MHD wave (Sec. 4.1)
-  diagnostics  FP64 reductions and shell spectra (Sec. 4.4)
+  diagnostics  FP64 reductions, shell spectra, dissipation spectra and energy transfer (Sec. 4.4)
+  validation   dispersion, dissipation and viscosity error measures of the wave tests (Sec. 4.3)
+  extended     the same step in extended precision, to expose the FP64 oracle's own rounding
 
 Parity pins live in tests/test_oracle_*.py. Unpinned beyond invariants: the forcing
 extension (momentum and field budgets are pinned; the scheme itself is not in the paper).
