@@ -15,11 +15,14 @@ paper's route), which stays stable on this workload. The variants time the same 
 the curl-stencil J (its kernel stages b tiles in LDS; the explicit stencil makes the Hall term
 linearly unstable at these parameters, so its state turns non-finite within about a hundred
 steps, which each variant reports), with d_i = 0 for the stencil kernel, with FP64 and FP16
-storage, and with the model variants (BGK fluid collision; electron MHD). Also reported: the
-roofline of the headline kernel (algorithmic bytes per launch over the event-timed average
-launch), the paper's own Orszag-Tang workload at 512^3 with the cost of the diagnostics, the
-reverse-mode cost on the adjoint workload, and the CPU oracle timed on a bounded sample on the
-host cores.
+storage, with the moment route at the other two Hall parameters of the forced configuration
+(d_i = 0 and 16), and with the model variants (BGK fluid collision; electron MHD). Also
+reported: the roofline of the headline kernel and of the FP64 step (algorithmic bytes per launch
+over the event-timed average launch) with the spread over the placement trials, the large
+configuration (1024^3 decaying turbulence, FP16 deviation storage, 500 steps, with an FP32 run
+for its spectral error), the paper's own Orszag-Tang workload at 512^3 with the cost of the
+diagnostics, the reverse-mode cost on the adjoint workload, and the CPU oracle timed on a bounded
+sample on the host cores.
 """
 
 from __future__ import annotations
@@ -133,6 +136,13 @@ def time_variant(n, storage, jmode, d_i, steps, warmup, fields, collision="centr
 
 
 NSHELLS = 33          # shell spectra 0..32 recorded after each timed run
+
+
+def sig(v, digits=4):
+    """v rounded to `digits` significant digits (None for a non-finite value)."""
+    if v is None or not math.isfinite(v):
+        return None
+    return float(f"{v:.{digits}g}")
 
 
 def spectral_error(spec, ref):
@@ -302,6 +312,82 @@ def adjoint_timing(n=128, storage="f32", jmode="moment", seg=50, recompute="stat
             "adjoint_ms_per_step": round(t_adj / seg, 4), "ratio": round((t_rec + t_adj) / t_fwd, 3)}
 
 
+LARGE_PHYS = dict(nu=5e-4, eta=5e-4, d_i=32.0, b0=(0.0, 0.0, 0.0))
+
+
+def large_configuration(n=1024, steps=500, every=100, nshells=17, placement_trials=8):
+    """The large configuration: n^3 decaying Hall-MHD turbulence (u and b seeded in shells 1..4,
+    rms 0.02 each, nu = eta = 5e-4, d_i = 32 cells, moment J, AA in place), FP16 deviation storage
+    with FP32 arithmetic, then the same run with FP32 storage as its reference; `steps` steps each,
+    event-timed in blocks of `every` with the FP64 reductions between blocks (outside the timing).
+    The state starts at equilibrium: the initial gradients (77 GB each at 1024^3) do not fit beside
+    the FP32 populations. Reports, per storage, ms per step, MLUPS, algorithmic GB/s and roofline
+    fraction, the first block whose reductions show a blown-up state, and the FP16-vs-FP32 error of
+    the final shell spectra. Skipped when the device lacks the memory of the FP32 run."""
+    import torch
+    import synthetic
+    from paper_2212_11024_amd.solver import Solver
+    need = 262e9        # FP32 populations (206 GB at 1024^3) beside u and b at initialisation
+    import gc
+    gc.collect()
+    torch.cuda.empty_cache()
+    free = torch.cuda.mem_get_info()[0]
+    if n == 1024 and free < need:
+        return {"skipped": f"needs {need / 1e9:.0f} GB of free HBM, {free / 1e9:.0f} GB free"}
+    shape = (n, n, n)
+    u, _ = synthetic.evaluate(synthetic.shell_field(0, 1, 4, 0.02), shape, "cuda", gradient=False)
+    b, _ = synthetic.evaluate(synthetic.shell_field(1, 1, 4, 0.02), shape, "cuda", gradient=False)
+    torch.cuda.empty_cache()
+    runs, spectra = [], {}
+    for storage in ("f16", "f32"):
+        print(f"[bench] large {n}^3 {storage}: {steps} steps", file=sys.stderr, flush=True)
+        s = Solver(n, n, n, LARGE_PHYS["nu"], LARGE_PHYS["eta"], LARGE_PHYS["d_i"], LARGE_PHYS["b0"], storage,
+                   "moment", "aa", u, b, placement_trials=placement_trials)
+        if storage == "f32":
+            del u, b
+            torch.cuda.empty_cache()
+        ms, first_bad = 0.0, None
+        stream = torch.cuda.current_stream()
+        for _ in range(steps // every):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            s.step(every)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms += e0.elapsed_time(e1)
+            red = s.reduce(allow_nonfinite=True)
+            if first_bad is None and (int(red[8]) > 0 or float(red[6]) >= 3 ** -0.5):
+                first_bad = s.steps
+        spectra[storage] = {f: s.spectrum(f, nshells) for f in ("u", "B")}
+        placement = s.placement_ms
+        taken = s.steps
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+        per = ms / taken
+        bpn = bytes_per_node(storage, forced=False)
+        gbps = bpn * n ** 3 / (per * 1e-3) / 1e9
+        runs.append({"storage": storage, "ms_per_step": per, "mlups": n ** 3 / (per * 1e-3) / 1e6,
+                     "bytes_per_node": bpn, "achieved_GBps": gbps, "frac": gbps / HBM_PEAK_GBPS,
+                     "steps": taken, "first_blown_up_step": first_bad,
+                     "E_kin": float(red[0]), "E_mag": float(red[1]),
+                     "placement_trials_ms": [round(t, 3) for t in placement] if placement else None})
+        print(f"[bench]   {per:.3f} ms/step, {runs[-1]['mlups']:.0f} MLUPS, {gbps:.0f} GB/s, first blown-up "
+              f"step {first_bad}", file=sys.stderr, flush=True)
+    err = {}
+    for f in ("u", "B"):
+        a, r = spectra["f16"][f], spectra["f32"][f]
+        rel = [float(abs(a[k] - r[k]) / r[k]) for k in range(1, 9)]
+        w = float((a[1:] - r[1:]).abs().sum() / r[1:].sum())
+        err[f] = {"max_rel_shells_1_4": sig(max(rel[:4])), "max_rel_shells_1_8": sig(max(rel)),
+                  "weighted_shells_1_16": sig(w)}
+    return {"workload": f"decaying Hall-MHD turbulence {n}^3, FP16 deviation storage (FP32 arithmetic, FP64 "
+                        f"reductions), moment J, AA, {steps} steps; FP32 storage as the reference",
+            "params": LARGE_PHYS, "runs": [{k: (sig(v, 6) if isinstance(v, float) else v) for k, v in r.items()}
+                                          for r in runs],
+            "spectral_error_f16_vs_f32": err}
+
+
 def copy_probe(gib=4, reps=5):
     """Plain device-to-device copy of a known size: achievable read+write bandwidth."""
     import torch
@@ -323,15 +409,15 @@ def copy_probe(gib=4, reps=5):
 
 
 def cpu_baseline(seconds=15.0):
-    """The FP64 oracle, as it stands, on a 32^3 sample of the workload's physics (moment-route J,
-    forced, like the headline) on the host cores: MLUPS = nodes x steps / time. The value is the
-    closed-form collision route with all threads (60% of the time budget); the T-matrix route
-    (the definition, 25%) and a single-thread run of the closed form (15%) are reported beside
-    it, with the host's CPU model."""
+    """The FP64 oracle, as it stands, on a 64^3 sample of the workload's physics (moment-route J,
+    forced, like the headline) on the host cores: MLUPS = nodes x steps / time, at least 5 timed
+    steps after one warm-up step. The value is the closed-form collision route with all threads
+    (60% of the time budget); the T-matrix route (the definition, 25%) and a single-thread run of
+    the closed form (15%) are reported beside it, with the host's CPU model."""
     import torch
     from oracle import scheme
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    n = 32
+    n = 64
     u, gu, b, gb, fu, fb = workload_fields(n, "cpu")
 
     def rate(route, budget, nthreads):
@@ -344,7 +430,7 @@ def cpu_baseline(seconds=15.0):
             st = scheme.step(st, p, 1)
             steps += 1
             el = time.perf_counter() - t0
-            if el >= budget:
+            if el >= budget and steps >= 5:
                 return n ** 3 * steps / el / 1e6, steps, el
 
     closed, steps, el = rate("closed", 0.60 * seconds, threads)
@@ -358,7 +444,7 @@ def cpu_baseline(seconds=15.0):
     except OSError:
         pass
     return {"value": closed, "unit": "MLUPS", "cores": threads, "kind": "oracle",
-            "sample": f"32^3 nodes, {steps} steps of the workload physics (moment J, forced), "
+            "sample": f"64^3 nodes, {steps} steps of the workload physics (moment J, forced), "
                       f"FP64 closed-form route, {el:.1f} s",
             "t_matrix_route_MLUPS": round(tmat[0], 4), "single_thread_MLUPS": round(single[0], 4),
             "host_cpu": model, "host_logical_cpus": os.cpu_count()}
@@ -381,6 +467,8 @@ def main(argv=None):
     ap.add_argument("--no-copy-probe", action="store_true",
                     help="skip the plain 4 GiB device copy (bandwidth reference and counter calibration)")
     ap.add_argument("--copy-probe", action="store_true", help="time the copy also with --variants headline/stencil")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the 1024^3 large configuration (FP16 and FP32 storage, 500 steps each)")
     ap.add_argument("--placement-trials", type=int, default=8,
                     help="candidate population buffers per timed run; the fastest over a 3-step probe is kept "
                          "(the step's speed depends on the physical memory behind the buffer)")
@@ -417,6 +505,8 @@ def main(argv=None):
         # while later draws were mostly fast (the trial times are reported for every run).
         variants = [("f32", "stencil", d_i), ("f32", "stencil", 0.0), ("f64", "moment", d_i),
                     ("f64", "stencil", d_i), ("f16", "moment", d_i), ("f16", "stencil", d_i),
+                    # the other two Hall parameters of the forced configuration (MHD to Hall-MHD)
+                    ("f32", "moment", 0.0), ("f32", "moment", 16.0),
                     # model variants of the same workload: BGK fluid collision, electron MHD
                     ("f32", "moment", d_i, "bgk", "hall"), ("f32", "moment", d_i, "central", "emhd")] + variants
     results = []
@@ -439,8 +529,7 @@ def main(argv=None):
         key = (r["jmode"], r["d_i"], r["collision"], r["magnetic"])
         if r["storage"] != "f64" and key in ref:
             err = spectral_error(sp, ref[key])
-            r["spectral_error_vs_f64"] = {f: {k: (round(v, 8) if math.isfinite(v) else None) for k, v in e.items()}
-                                          for f, e in err.items()}
+            r["spectral_error_vs_f64"] = {f: {k: sig(v) for k, v in e.items()} for f, e in err.items()}
     ot = []
     if args.variants == "all":
         for st in ("f64", "f32"):
@@ -449,6 +538,9 @@ def main(argv=None):
             ot.append(orszag_tang_timing(n, st, args.steps, args.warmup, args.placement_trials))
             print(f"[bench]   {ot[-1]['ms_per_step']:.3f} ms/step, {ot[-1]['mlups']:.0f} MLUPS", file=sys.stderr,
                   flush=True)
+    large = None
+    if args.variants == "all" and not args.no_large:
+        large = large_configuration(placement_trials=args.placement_trials)
     adj = []
     if args.variants == "all":
         for jm, rc in adjoint_cases:
@@ -456,11 +548,33 @@ def main(argv=None):
             adj.append(adjoint_timing(128, "f32", jm, recompute=rc))
             print(f"[bench]   {adj[-1]}", file=sys.stderr, flush=True)
     head = results[0]
-    traffic = None
-    rec = TRAFFIC_RECORDS.get((head["storage"], head["jmode"]))
-    if (n == 512 and rec and (head["collision"], head["magnetic"]) == ("central", "hall")
-            and kernel_fingerprint() == rec["fingerprint"]):
-        traffic = rec["GB_per_launch"]
+
+    def traffic_of(r):
+        rec = TRAFFIC_RECORDS.get((r["storage"], r["jmode"]))
+        if (n == 512 and rec and (r["collision"], r["magnetic"]) == ("central", "hall") and r["d_i"] == d_i
+                and kernel_fingerprint() == rec["fingerprint"]):
+            return rec["GB_per_launch"]
+        return None
+
+    def placement_spread(r):
+        """Roofline fraction of each placement trial (3-step probes from the initial state) on the
+        algorithmic bytes: best, median and worst buffer drawn."""
+        trials = sorted(r.get("placement_trials_ms") or [])
+        if not trials:
+            return None
+        frac = [r["bytes_per_node"] * n ** 3 / (t * 1e-3) / 1e9 / HBM_PEAK_GBPS for t in trials]
+        return {"trials": len(trials), "best": sig(frac[0]), "median": sig(frac[len(frac) // 2]),
+                "worst": sig(frac[-1])}
+
+    def roofline_of(r):
+        return {"bound": "hbm", "achieved": round(r["achieved_GBps"], 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": round(r["achieved_GBps"] / HBM_PEAK_GBPS, 4), "traffic": traffic_of(r),
+                "traffic_unit": "GB per launch (measured HBM bytes)",
+                "algorithmic_GB_per_launch": round(r["bytes_per_node"] * n ** 3 / 1e9, 3),
+                "bytes_per_node": r["bytes_per_node"], "placement_trial_frac": placement_spread(r)}
+
+    f64_head = next((r for r in results if (r["storage"], r["jmode"], r["d_i"], r["collision"], r["magnetic"])
+                     == ("f64", "moment", d_i, "central", "hall")), None)
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
@@ -486,14 +600,14 @@ def main(argv=None):
                    "forcing": "static, |k| <= 2, rms 1e-5",
                    "placement": f"fastest of up to {args.placement_trials} population buffers over a 3-step "
                                 "probe each (trial timings in the variants' placement_trials_ms)"},
-        "roofline": {"bound": "hbm", "achieved": round(head["achieved_GBps"], 1), "peak": HBM_PEAK_GBPS,
-                     "unit": "GB/s", "frac": round(head["achieved_GBps"] / HBM_PEAK_GBPS, 4),
-                     "traffic": traffic, "traffic_unit": "GB per launch (measured HBM bytes)",
-                     "algorithmic_GB_per_launch": round(head["bytes_per_node"] * n ** 3 / 1e9, 3),
-                     "bytes_per_node": head["bytes_per_node"],
+        "roofline": {**roofline_of(head),
                      "copy_GBps_same_box": copy["GBps"] if copy else None,
                      "frac_of_copy": round(head["achieved_GBps"] / copy["GBps"], 4) if copy else None},
+        # the paper's precision: the same step with FP64 storage and arithmetic
+        "roofline_f64": ({**roofline_of(f64_head), "ms_per_step": round(f64_head["ms_per_step"], 4),
+                          "mlups": round(f64_head["mlups"], 1)} if f64_head else None),
         "variants": [{k: (float(f"{v:.6g}") if isinstance(v, float) else v) for k, v in r.items()} for r in results],
+        "large": large,
         "adjoint_forward_ratio": (adj[0]["ratio"] if adj else None),
         "adjoint": adj,
         "copy_probe": copy,

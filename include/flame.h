@@ -52,6 +52,8 @@ typedef int32_t flame_status;
 #define FLAME_E_HIP (-3)         /* a HIP / hipFFT call failed (message names it) */
 #define FLAME_E_NONFINITE (-4)   /* a population is NaN or infinite (flame_reduce) */
 #define FLAME_E_UNSUPPORTED (-5) /* option combination not built */
+#define FLAME_E_UNSTABLE (-6)    /* finite, but max|u| >= c_s = 1/sqrt(3): the run has left the
+                                    weakly compressible regime the scheme is built for (flame_reduce) */
 #define FLAME_W_CFL 1            /* advisory whistler bound pi * d_i * max|B| > 1 exceeded */
 
 /* Storage precision of the populations. Values are stored as deviations from the rest
@@ -158,13 +160,17 @@ flame_status flame_moments(flame_ctx* c, double* rho, double* u, double* b, doub
                            double* divb);
 
 /* FP64 global reductions (slots above) into host out[FLAME_NRED]. Synchronises. Returns
- * FLAME_E_NONFINITE (after filling out) if any population is non-finite. Fixed-order
- * tree sums: bitwise reproducible for a given grid and state. */
+ * FLAME_E_NONFINITE (after filling out) if any population is non-finite, else
+ * FLAME_E_UNSTABLE (after filling out) if max|u| (slot 6) reaches the lattice sound speed
+ * c_s = 1/sqrt(3): the equilibria of Sec. 3.1 are expansions in the Mach number, and a flow at
+ * Mach one is a blow-up, not a solution. Fixed-order tree sums and a fixed-order merge of the
+ * block partials: bitwise reproducible for a given grid and state. */
 flame_status flame_reduce(flame_ctx* c, double* out);
 
 /* Shell energy spectrum of u (field = 0) or B (field = 1) into host e_k[nshells]:
  * E(s) = 1/2 sum_{round(|k|) = s} |v_hat(k)|^2, v_hat = DFT(v) / ncell, k the signed integer
- * wavevector (paper Sec. 4.4 spectra). FP64 FFT (hipFFT) and binning. Synchronises. The first
+ * wavevector (paper Sec. 4.4 spectra). FP64 FFT (hipFFT) and binning in a fixed order (no
+ * atomics), so the spectrum of a given state is bitwise reproducible. Synchronises. The first
  * call allocates a workspace of one node field and one half spectrum (kept until flame_destroy);
  * FLAME_E_NOMEM if that fails, and a later call tries again. */
 flame_status flame_spectrum(flame_ctx* c, int32_t field, int32_t nshells, double* e_k);
@@ -192,7 +198,8 @@ flame_status flame_dissipation_spectrum(flame_ctx* c, int32_t field, int32_t nsh
  * terms, d/dt sum_{s < k} E(s) = -S_MHD(k) - D(k) with D from flame_dissipation_spectrum (with the
  * Hall term, -sum_{s < k} t_hall is added to the right-hand side).
  * Derivatives are spectral, q_a = 2 pi k_a / n_a, and 0 on the Nyquist index of an even axis;
- * products are formed node by node. FP64 throughout (hipFFT). Allocates 11 node fields and 7
+ * products are formed node by node. FP64 throughout (hipFFT), shell sums in a fixed order
+ * (bitwise reproducible for a given state). Allocates 11 node fields and 7
  * half spectra of device memory for the call (19 GB at 512^3) and frees them before returning;
  * FLAME_E_NOMEM if that fails. FLAME_E_INVAL for nshells outside 1..4096 or a NULL t_adv, t_lor
  * or t_ind. Synchronises. */
@@ -238,7 +245,9 @@ flame_status flame_adjoint_step(flame_ctx* c, const void* state, const void* lam
  * at x - c_q. flame_trace_bytes(c) bytes each (0 if c is NULL). flame_trace_export writes the
  * current state (exact: stored values are moved, not recoded); flame_trace_step advances a
  * lattice src by one step into dst (dst must not alias src) without touching the context, and
- * reproduces the context's own steps bitwise. Other routes and layouts get FLAME_E_UNSUPPORTED. */
+ * reproduces the context's own steps bitwise. Other routes and layouts (the stencil route, the AB
+ * layout) get FLAME_E_UNSUPPORTED from all three calls that take a lattice, and nothing is
+ * launched. */
 size_t flame_trace_bytes(const flame_ctx* c);
 flame_status flame_trace_export(flame_ctx* c, void* lat);
 flame_status flame_trace_step(flame_ctx* c, const void* src, void* dst);
@@ -246,7 +255,7 @@ flame_status flame_trace_step(flame_ctx* c, const void* src, void* dst);
 /* Moment route: lam = (d step / d x)^T lam_next for the step whose pre-collision state is the
  * trace lattice src pulled (the step flame_trace_step takes from src), with J recomputed from
  * that state; the same reverse pass as flame_adjoint_step without a saved state. lam, lam_next
- * as for flame_adjoint_step; lam must not alias lam_next. The stencil route gets
+ * as for flame_adjoint_step; lam must not alias lam_next. The stencil route and the AB layout get
  * FLAME_E_UNSUPPORTED. */
 flame_status flame_adjoint_trace_step(flame_ctx* c, const void* src, const void* lam_next, void* lam);
 

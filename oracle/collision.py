@@ -145,3 +145,29 @@ def collide_bgk_closed(f, rho, U, B, omega, F=None):
             out = out + (1.0 - 0.5 * omega) * F[a] * unit_central_moment_dist(U, p)
     return out
 
+
+
+def guo_force_dist(U, lat):
+    """Second-order Hermite form of the distributions with a unit first central moment along
+    each axis (and zero mass and second central moment), on a velocity set without the D3Q27
+    corners: phi^a_i = w_i [(c_ia - U_a) / c_s^2 + (c_i . U) c_ia / c_s^4]. Returns (3, q, n)."""
+    from .lattice import CS2
+    c = lat.c.T.unsqueeze(-1)                                   # (3, q, 1)
+    w = lat.w.view(1, -1, 1)
+    cu = (c * U.unsqueeze(1)).sum(0, keepdim=True)             # (1, q, n)
+    return w * ((c - U.unsqueeze(1)) / CS2 + cu * c / CS2 ** 2)
+
+
+def collide_bgk_second_order(f, rho, U, B, omega, lat, F=None):
+    """BGK collision (S = omega I, Sec. 3.1.1) on a fluid set without the D3Q27 corners, towards
+    its second-order equilibrium with the Maxwell-stress term, f0 + (1 - omega)(f - f0); a body
+    force adds (1 - omega/2) F_a phi^a (guo_force_dist), which, with U carrying F/(2 rho), ends
+    the first central moments at +F/2 as in the D3Q27 operators. f: (q, n)."""
+    from .equilibrium import f_mhd_eq_lattice
+    f0 = f_mhd_eq_lattice(rho, U, B, lat)
+    out = f0 + (1.0 - omega) * (f - f0)
+    if F is not None:
+        phi = guo_force_dist(U, lat)
+        for a in range(3):
+            out = out + (1.0 - 0.5 * omega) * F[a] * phi[a]
+    return out

@@ -9,7 +9,8 @@
   unchanged mass and momentum). It is read as the Hermite projection of that stated
   moment: (w/2c_s^4) M : (c c - c_s^2 I) with M = 1/2 |B|^2 I - B B.
 * g_eq_hall: the vector-valued D3Q7 equilibrium with the Hall correction U -> U - alpha_H J
-  (eq. gHall_eq).
+  (eq. gHall_eq), also on the D3Q15 / D3Q27 magnetic variants.
+* f_eq2: the second-order equilibrium of the D3Q19 fluid variant.
 
 Shapes: scalars (...), vectors (3, ...), populations (27, ...) or (7, 3, ...).
 """
@@ -62,19 +63,39 @@ def f_eq(rho, U):
     return _bc(W, rho) * rho * bracket
 
 
-def maxwell_term(B):
-    """Lorentz-force part of the fluid equilibrium: (w/2c_s^4) M:(cc - c_s^2 I)."""
+def maxwell_term(B, c=C, w=W):
+    """Lorentz-force part of the fluid equilibrium: (w/2c_s^4) M:(cc - c_s^2 I), on the velocity
+    set c with weights w (the paper's D3Q27 by default)."""
     bx, by, bz = B[0], B[1], B[2]
     b2 = bx * bx + by * by + bz * bz
     M = [[0.5 * b2 - bx * bx, -bx * by, -bx * bz],
          [-by * bx, 0.5 * b2 - by * by, -by * bz],
          [-bz * bx, -bz * by, 0.5 * b2 - bz * bz]]
-    out = torch.zeros((27,) + tuple(bx.shape), dtype=bx.dtype)
+    out = torch.zeros((c.shape[0],) + tuple(bx.shape), dtype=bx.dtype)
     for a in range(3):
         for b in range(3):
-            proj = _bc(C[:, a] * C[:, b] - (CS2 if a == b else 0.0), bx)
+            proj = _bc(c[:, a] * c[:, b] - (CS2 if a == b else 0.0), bx)
             out = out + proj * M[a][b]
-    return _bc(W, bx) / (2 * CS2 ** 2) * out
+    return _bc(w, bx) / (2 * CS2 ** 2) * out
+
+
+def f_eq2(rho, U, c, w):
+    """Second-order Hermite equilibrium on a velocity set without the D3Q27 corners (D3Q19):
+    w rho (1 + c.U / c_s^2 + (c.U)^2 / (2 c_s^4) - |U|^2 / (2 c_s^2)), the truncation of the
+    App. A expansion at the highest order whose Hermite polynomials such a set represents with
+    the continuous-weight norms (its mass, momentum and momentum flux rho U U + rho c_s^2 I are
+    exact)."""
+    cu = _bc(c[:, 0], rho) * U[0] + _bc(c[:, 1], rho) * U[1] + _bc(c[:, 2], rho) * U[2]
+    u2 = U[0] * U[0] + U[1] * U[1] + U[2] * U[2]
+    return _bc(w, rho) * rho * (1.0 + cu / CS2 + cu * cu / (2 * CS2 ** 2) - u2 / (2 * CS2))
+
+
+def f_mhd_eq_lattice(rho, U, B, lat):
+    """f^mhd(0)(rho, U, B) on the fluid lattice lat: the paper's sixth-order D3Q27 form, or the
+    second-order form on D3Q19; both with the Maxwell-stress term."""
+    if lat.name == "d3q27":
+        return f_mhd_eq(rho, U, B)
+    return f_eq2(rho, U, lat.c, lat.w) + maxwell_term(B, lat.c, lat.w)
 
 
 def f_mhd_eq(rho, U, B):
@@ -82,13 +103,14 @@ def f_mhd_eq(rho, U, B):
     return f_eq(rho, U) + maxwell_term(B)
 
 
-def g_eq_hall(U, B, J, alpha_h):
-    """Hall-MHD magnetic equilibrium, eq. gHall_eq; returns (7, 3, ...).
+def g_eq_hall(U, B, J, alpha_h, xi=XI, wm=WM):
+    """Hall-MHD magnetic equilibrium, eq. gHall_eq; returns (M, 3, ...) on the magnetic velocity
+    set xi with weights wm (the paper's D3Q7 by default).
 
     g_{i,a} = W_i (B_a + xi_{i,b} (V_b B_a - B_b V_a) / C^2) with V = U - alpha_H J.
     """
     V = U - alpha_h * J
-    xv = torch.einsum("ib,b...->i...", XI, V)       # xi_i . V
-    xb = torch.einsum("ib,b...->i...", XI, B)       # xi_i . B
+    xv = torch.einsum("ib,b...->i...", xi, V)       # xi_i . V
+    xb = torch.einsum("ib,b...->i...", xi, B)       # xi_i . B
     g = B.unsqueeze(0) + (xv.unsqueeze(1) * B.unsqueeze(0) - xb.unsqueeze(1) * V.unsqueeze(0)) / C2
-    return WM.view(7, *([1] * B.dim())) * g
+    return wm.view(xi.shape[0], *([1] * B.dim())) * g

@@ -22,6 +22,15 @@ With forcing, -F/2 and -S/2 are added so that the node moments return exactly u 
 Variants (Params.collision, Params.magnetic): the BGK fluid collision, which is the same step
 with S = omega I (Sec. 3.1.2); and electron MHD (Sec. 6), whose magnetic equilibrium, the J
 system built on it and the initial magnetic state take the bulk velocity as zero.
+
+Lattice variants (Params.fluid_lattice, Params.magnetic_lattice; readings in oracle.lattice):
+the D3Q19 fluid set, which carries the BGK collision towards its second-order equilibrium with
+the Maxwell-stress term (the central-moment operator of Sec. 3.1.2 is built on the 27-moment
+basis of D3Q27), and the D3Q15 / D3Q27 magnetic sets, with the same Hall equilibrium and BGK
+collision as D3Q7. The state then holds (q, ...) fluid and (m, 3, ...) magnetic populations.
+For D3Q19 the initial non-equilibrium part is the second-order Hermite projection
+(w / 2 c_s^4) P:(c c - c_s^2 I) of the same deviatoric moment P, and the forcing shift
+-F/2 of the first central moments uses the second-order form of oracle.collision.guo_force_dist.
 """
 
 from __future__ import annotations
@@ -33,8 +42,8 @@ import torch
 
 from . import collision
 from .current import current_moment, current_stencil, divergence_moment
-from .equilibrium import f_mhd_eq, g_eq_hall
-from .lattice import C, CS2, DT, WM, XI, omega_fluid, omega_magnetic
+from .equilibrium import f_mhd_eq_lattice, g_eq_hall
+from .lattice import CS2, DT, FLUID_LATTICES, MAGNETIC_LATTICES, omega_fluid, omega_magnetic
 
 
 @dataclasses.dataclass
@@ -56,6 +65,17 @@ class Params:
     # magnetic equilibrium: "hall" (eq. gHall_eq, V = U - alpha_H J) or "emhd" (electron MHD,
     # Sec. 6: the bulk velocity neglected against the Hall current, V = -alpha_H J)
     magnetic: str = "hall"
+    # velocity sets: the paper's D3Q27 fluid and D3Q7 magnetic, or the variants of oracle.lattice
+    fluid_lattice: str = "d3q27"
+    magnetic_lattice: str = "d3q7"
+
+    @property
+    def fl(self):
+        return FLUID_LATTICES[self.fluid_lattice]
+
+    @property
+    def ml(self):
+        return MAGNETIC_LATTICES[self.magnetic_lattice]
 
     @property
     def omega(self):
@@ -76,8 +96,8 @@ class Params:
 
 @dataclasses.dataclass
 class State:
-    f: torch.Tensor   # (27, nz, ny, nx)
-    g: torch.Tensor   # (7, 3, nz, ny, nx)
+    f: torch.Tensor   # (27, nz, ny, nx); (q, ...) on a fluid variant
+    g: torch.Tensor   # (7, 3, nz, ny, nx); (m, 3, ...) on a magnetic variant
 
     def clone(self):
         return State(self.f.clone(), self.g.clone())
@@ -86,14 +106,14 @@ class State:
 def moments(st: State, p: Params):
     """rho (nz,ny,nx), U (3,...), B (3,...), Lambda (3,3,...)."""
     rho = st.f.sum(0)
-    mom = torch.einsum("i...,ia->a...", st.f, C)
+    mom = torch.einsum("i...,ia->a...", st.f, p.fl.c)
     if p.force_u is not None:
         mom = mom + 0.5 * p.force_u
     U = mom / rho
     B = st.g.sum(0)
     if p.force_b is not None:
         B = B + 0.5 * p.force_b
-    Lam = torch.einsum("ia,ib...->ab...", XI, st.g)
+    Lam = torch.einsum("ia,ib...->ab...", p.ml.c, st.g)
     return rho, U, B, Lam
 
 
@@ -126,35 +146,44 @@ def collide(st: State, p: Params) -> State:
     J = current(p, Um, B, Lam)
     n = p.ncell
     F = None if p.force_u is None else p.force_u.reshape(3, n)
-    args = (st.f.reshape(27, n), rho.reshape(n), U.reshape(3, n), B.reshape(3, n), p.omega)
+    q = p.fl.q
+    args = (st.f.reshape(q, n), rho.reshape(n), U.reshape(3, n), B.reshape(3, n), p.omega)
     if p.collision not in ("central", "bgk"):
         raise ValueError(p.collision)
-    if p.route == "T":
+    if p.fluid_lattice != "d3q27":
+        if p.collision != "bgk":
+            raise ValueError("the central-moment collision is defined on D3Q27 only")
+        fs = collision.collide_bgk_second_order(*args, p.fl, F=F)
+    elif p.route == "T":
         rates = torch.full((27,), p.omega, dtype=DT) if p.collision == "bgk" else None
         fs = collision.collide_T(*args, F=F, rates=rates)
     elif p.route == "closed":
         fs = (collision.collide_bgk_closed if p.collision == "bgk" else collision.collide_closed)(*args, F=F)
     else:
         raise ValueError(p.route)
-    geq = g_eq_hall(Um, B, J, p.d_i)
+    ml = p.ml
+    geq = g_eq_hall(Um, B, J, p.d_i, ml.c, ml.w)
     gs = st.g - p.omega_b * (st.g - geq)
     if p.force_b is not None:
-        gs = gs + (1.0 - 0.5 * p.omega_b) * WM.view(7, 1, 1, 1, 1) * p.force_b.unsqueeze(0)
+        gs = gs + (1.0 - 0.5 * p.omega_b) * ml.w.view(ml.q, 1, 1, 1, 1) * p.force_b.unsqueeze(0)
     return State(fs.reshape(st.f.shape), gs)
 
 
-def stream(st: State) -> State:
-    """f_i(x + c_i) <- f*_i(x); g_i(x + xi_i) <- g*_i(x), periodic."""
-    f = torch.stack([torch.roll(st.f[i], shifts=(int(C[i, 2]), int(C[i, 1]), int(C[i, 0])),
-                                dims=(0, 1, 2)) for i in range(27)])
-    g = torch.stack([torch.roll(st.g[i], shifts=(int(XI[i, 2]), int(XI[i, 1]), int(XI[i, 0])),
-                                dims=(1, 2, 3)) for i in range(7)])
+def stream(st: State, p: Optional[Params] = None) -> State:
+    """f_i(x + c_i) <- f*_i(x); g_i(x + xi_i) <- g*_i(x), periodic (on the lattices of p; the
+    paper's D3Q27 / D3Q7 without p)."""
+    fc = FLUID_LATTICES["d3q27"].c if p is None else p.fl.c
+    mc = MAGNETIC_LATTICES["d3q7"].c if p is None else p.ml.c
+    f = torch.stack([torch.roll(st.f[i], shifts=(int(fc[i, 2]), int(fc[i, 1]), int(fc[i, 0])),
+                                dims=(0, 1, 2)) for i in range(fc.shape[0])])
+    g = torch.stack([torch.roll(st.g[i], shifts=(int(mc[i, 2]), int(mc[i, 1]), int(mc[i, 0])),
+                                dims=(1, 2, 3)) for i in range(mc.shape[0])])
     return State(f, g)
 
 
 def step(st: State, p: Params, nsteps: int = 1) -> State:
     for _ in range(nsteps):
-        st = stream(collide(st, p))
+        st = stream(collide(st, p), p)
     return st
 
 
@@ -180,13 +209,14 @@ def init_state(p: Params, u, b, grad_u=None, grad_b=None, noneq=True) -> State:
     """
     n = p.ncell
     sh = p.shape
+    fl, ml = p.fl, p.ml
     b0 = torch.tensor(p.b0, dtype=DT).view(3, 1, 1, 1)
     B = b + b0
     rho = torch.ones(sh, dtype=DT)
-    f = f_mhd_eq(rho, u, B)
+    f = f_mhd_eq_lattice(rho, u, B, fl)
     J = torch.zeros_like(u) if grad_b is None else curl_from_gradient(grad_b)
-    g = g_eq_hall(magnetic_velocity(p, u), B, J, p.d_i)
-    kneq = torch.zeros((n, 27), dtype=DT)
+    g = g_eq_hall(magnetic_velocity(p, u), B, J, p.d_i, ml.c, ml.w)
+    P = None
     if noneq and grad_u is not None:
         s = grad_u + grad_u.transpose(0, 1)
         div = grad_u[0, 0] + grad_u[1, 1] + grad_u[2, 2]
@@ -194,20 +224,37 @@ def init_state(p: Params, u, b, grad_u=None, grad_b=None, noneq=True) -> State:
         for a in range(3):
             P[a, a] = P[a, a] + (CS2 / p.omega) * (2.0 / 3.0) * div
         P = P.reshape(3, 3, n)
-        kneq[:, 4], kneq[:, 5], kneq[:, 6] = P[0, 1], P[0, 2], P[1, 2]
-        kneq[:, 7], kneq[:, 8] = P[0, 0] - P[1, 1], P[0, 0] - P[2, 2]
-    if p.force_u is not None:
-        kneq[:, 1:4] = -0.5 * p.force_u.reshape(3, n).T
-    if bool(torch.any(kneq != 0)):
-        f = f + collision.moments_to_dist(u.reshape(3, n), kneq).reshape((27,) + sh)
+    if fl.name == "d3q27":
+        kneq = torch.zeros((n, 27), dtype=DT)
+        if P is not None:
+            kneq[:, 4], kneq[:, 5], kneq[:, 6] = P[0, 1], P[0, 2], P[1, 2]
+            kneq[:, 7], kneq[:, 8] = P[0, 0] - P[1, 1], P[0, 0] - P[2, 2]
+        if p.force_u is not None:
+            kneq[:, 1:4] = -0.5 * p.force_u.reshape(3, n).T
+        if bool(torch.any(kneq != 0)):
+            f = f + collision.moments_to_dist(u.reshape(3, n), kneq).reshape((27,) + sh)
+    else:
+        # second-order Hermite projections of the same non-equilibrium moments
+        fq = f.reshape(fl.q, n)
+        if P is not None:
+            for a in range(3):
+                for bb in range(3):
+                    proj = (fl.c[:, a] * fl.c[:, bb] - (CS2 if a == bb else 0.0)).view(-1, 1)
+                    fq = fq + fl.w.view(-1, 1) / (2 * CS2 ** 2) * proj * P[a, bb].view(1, n)
+        if p.force_u is not None:
+            phi = collision.guo_force_dist(u.reshape(3, n), fl)
+            F = p.force_u.reshape(3, n)
+            for a in range(3):
+                fq = fq - 0.5 * F[a] * phi[a]
+        f = fq.reshape((fl.q,) + sh)
     if noneq and grad_b is not None:
-        for i in range(7):
+        for i in range(ml.q):
             for bb in range(3):
-                s = sum(XI[i, a] * grad_b[a, bb] for a in range(3) if XI[i, a] != 0)
+                s = sum(ml.c[i, a] * grad_b[a, bb] for a in range(3) if ml.c[i, a] != 0)
                 if not isinstance(s, int):
-                    g[i, bb] = g[i, bb] - (1.0 / p.omega_b) * WM[i] * s
+                    g[i, bb] = g[i, bb] - (1.0 / p.omega_b) * ml.w[i] * s
     if p.force_b is not None:
-        g = g - 0.5 * WM.view(7, 1, 1, 1, 1) * p.force_b.unsqueeze(0)
+        g = g - 0.5 * ml.w.view(ml.q, 1, 1, 1, 1) * p.force_b.unsqueeze(0)
     return State(f, g)
 
 

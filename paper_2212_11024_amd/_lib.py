@@ -18,6 +18,7 @@ FLAME_E_NOMEM = -2
 FLAME_E_HIP = -3
 FLAME_E_NONFINITE = -4
 FLAME_E_UNSUPPORTED = -5
+FLAME_E_UNSTABLE = -6
 FLAME_W_CFL = 1
 
 FLAME_F64, FLAME_F32, FLAME_F16 = 0, 1, 2
@@ -136,9 +137,11 @@ def flame_moments(ctx: int, rho: int, u: int, b: int, j: int, divb: int) -> int:
 
 
 def flame_reduce(ctx: int, allow_nonfinite: bool = False):
+    """(status, out[FLAME_NRED]). allow_nonfinite: a blown-up state (FLAME_E_NONFINITE or
+    FLAME_E_UNSTABLE) is returned with its status instead of raising."""
     out = (ctypes.c_double * FLAME_NRED)()
     code = load().flame_reduce(ctx, out)
-    if not (allow_nonfinite and code == FLAME_E_NONFINITE):
+    if not (allow_nonfinite and code in (FLAME_E_NONFINITE, FLAME_E_UNSTABLE)):
         _check(code, ctx)
     return code, list(out)
 

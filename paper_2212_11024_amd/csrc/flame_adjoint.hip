@@ -343,8 +343,8 @@ flame_status flame_trace_step(flame_ctx* c, const void* src, void* dst) {
     c->err = "reverse mode is built for the paper's model only (central-moment fluid, Hall equilibrium)";
     return FLAME_E_UNSUPPORTED;
   }
-  if (c->p.jmode != FLAME_J_MOMENT) {
-    c->err = "trace step is available on the moment route only";
+  if (c->p.jmode != FLAME_J_MOMENT || c->p.layout != FLAME_LAYOUT_AA) {
+    c->err = "trace step is available on the moment route with the AA layout only";
     return FLAME_E_UNSUPPORTED;
   }
   if (!src || !dst || src == dst) {
@@ -392,8 +392,8 @@ flame_status flame_adjoint_trace_step(flame_ctx* c, const void* src, const void*
     c->err = "reverse mode is built for the paper's model only (central-moment fluid, Hall equilibrium)";
     return FLAME_E_UNSUPPORTED;
   }
-  if (c->p.jmode != FLAME_J_MOMENT) {
-    c->err = "the trace adjoint is available on the moment route only";
+  if (c->p.jmode != FLAME_J_MOMENT || c->p.layout != FLAME_LAYOUT_AA) {
+    c->err = "the trace adjoint is available on the moment route with the AA layout only";
     return FLAME_E_UNSUPPORTED;
   }
   if (!src || !lam_next || !lam || lam == lam_next) {

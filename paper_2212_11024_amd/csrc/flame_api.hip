@@ -419,6 +419,24 @@ __global__ __launch_bounds__(kRedThreads) void reduce_kernel(AuxArgs<S> a, doubl
   if (threadIdx.x < FLAME_NRED) partials[blockIdx.x * FLAME_NRED + threadIdx.x] = sh[threadIdx.x][0];
 }
 
+// Fixed-order merge of the block partials of reduce_kernel into the FLAME_NRED results: thread k
+// runs over the blocks in order for slot k (sums; maxima for slots 4 and 6) and normalises the
+// slot as flame_reduce documents (node averages, rms, plain sums and maxima).
+__global__ __launch_bounds__(64) void reduce_merge_kernel(const double* partials, int blocks, double n,
+                                                          double* out) {
+  const int k = threadIdx.x;
+  if (k >= FLAME_NRED) return;
+  double acc = 0.0;
+  for (int b = 0; b < blocks; ++b) {
+    const double v = partials[static_cast<size_t>(b) * FLAME_NRED + k];
+    acc = (k == 4 || k == 6) ? fmax(acc, v) : acc + v;
+  }
+  if (k <= 3) acc = acc / n;
+  else if (k == 5 || k == 7) acc = sqrt(acc / n);
+  out[k] = acc;
+}
+
+
 // ------------------------------------------------------------------ spectra
 template <typename S>
 __global__ __launch_bounds__(256) void field_component_kernel(AuxArgs<S> a, int field, int comp, double* out) {
@@ -441,43 +459,93 @@ __global__ __launch_bounds__(256) void field_component_kernel(AuxArgs<S> a, int 
   }
 }
 
-constexpr int kSpecThreads = 256;
 constexpr int kSpecShellsMax = 4096;
 
 __device__ __forceinline__ int signed_freq(int idx, int n) { return idx <= (n - 1) / 2 ? idx : idx - n; }
 
+// Shell binning without atomics. A binning block is one wavefront; it visits its entries in the
+// fixed order of a grid-stride loop, 64 at a time, and adds each group's contributions shell by
+// shell: the lanes holding one shell are summed by a fixed tree across the wavefront (the other
+// lanes contribute +0), and lane 0 adds that sum to the block's LDS bins, which only it writes.
+// The block partials are then merged in block order (bin_merge_kernel). Every sum therefore has
+// one fixed order for a given grid, and spectra are bitwise reproducible.
+constexpr int kBinThreads = 64;
+constexpr int kBinBlocksMax = 2048;
+
+// Lane 0 receives the sum of x over the 64 lanes, in a fixed tree order.
+__device__ __forceinline__ double wave_sum_fixed(double x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, kBinThreads);
+  return x;
+}
+
+// Add v to bins[shell] for every lane (shell < 0: nothing). Called by all 64 lanes together.
+__device__ __forceinline__ void bin_group(double* bins, int shell, double v) {
+  unsigned long long pending = __ballot(shell >= 0);
+  while (pending) {
+    const int leader = __ffsll(static_cast<long long>(pending)) - 1;
+    const int s = __shfl(shell, leader, kBinThreads);
+    const bool mine = shell == s;
+    const double sum = wave_sum_fixed(mine ? v : 0.0);
+    if (threadIdx.x == 0) bins[s] += sum;
+    pending &= ~__ballot(mine);
+  }
+}
+
 // Half-spectrum (nz, ny, nx/2+1) of an r2c transform; each entry stands for itself and, for
 // 0 < kx < nx - kx, its conjugate mirror at -k (same shell). Each entry adds w |X|^2 norm2 to
 // its shell: w = 1/2 for the energy spectrum; w = |q|^2, q_a = 2 pi k_a / n_a, for the
-// dissipation spectrum (k2 set).
-__global__ __launch_bounds__(kSpecThreads) void shell_bin_kernel(const hipfftDoubleComplex* X, int nx, int ny,
-                                                                 int nz, int nshells, double norm2, int k2,
-                                                                 double* partials) {
+// dissipation spectrum (k2 set). Block partials [gridDim.x][nshells].
+__global__ __launch_bounds__(kBinThreads) void shell_bin_kernel(const hipfftDoubleComplex* X, int nx, int ny,
+                                                                int nz, int nshells, double norm2, int k2,
+                                                                double* partials) {
   extern __shared__ double bins[];
   for (int s = threadIdx.x; s < nshells; s += blockDim.x) bins[s] = 0.0;
   __syncthreads();
   const int nxh = nx / 2 + 1;
   const size_t total = static_cast<size_t>(nz) * ny * nxh;
   const size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
-  for (size_t k = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; k < total; k += stride) {
-    const int kx = static_cast<int>(k % nxh);
-    const size_t r = k / nxh;
-    const int ky = static_cast<int>(r % ny);
-    const int kz = static_cast<int>(r / ny);
-    const double fx = kx, fy = signed_freq(ky, ny), fz = signed_freq(kz, nz);
-    const int shell = static_cast<int>(floor(sqrt(fx * fx + fy * fy + fz * fz) + 0.5));
-    if (shell >= nshells) continue;
-    const double re = X[k].x, im = X[k].y;
-    const double mult = (kx == 0 || 2 * kx == nx) ? 1.0 : 2.0;
-    double w = 0.5;
-    if (k2) {
-      const double qx = (2.0 * M_PI / nx) * fx, qy = (2.0 * M_PI / ny) * fy, qz = (2.0 * M_PI / nz) * fz;
-      w = qx * qx + qy * qy + qz * qz;
+  // the loop bound is uniform over the wavefront, so every lane takes part in every group
+  for (size_t base = static_cast<size_t>(blockIdx.x) * blockDim.x; base < total; base += stride) {
+    const size_t k = base + threadIdx.x;
+    int shell = -1;
+    double v = 0.0;
+    if (k < total) {
+      const int kx = static_cast<int>(k % nxh);
+      const size_t r = k / nxh;
+      const int ky = static_cast<int>(r % ny);
+      const int kz = static_cast<int>(r / ny);
+      const double fx = kx, fy = signed_freq(ky, ny), fz = signed_freq(kz, nz);
+      shell = static_cast<int>(floor(sqrt(fx * fx + fy * fy + fz * fz) + 0.5));
+      if (shell < nshells) {
+        const double re = X[k].x, im = X[k].y;
+        const double mult = (kx == 0 || 2 * kx == nx) ? 1.0 : 2.0;
+        double w = 0.5;
+        if (k2) {
+          const double qx = (2.0 * M_PI / nx) * fx, qy = (2.0 * M_PI / ny) * fy, qz = (2.0 * M_PI / nz) * fz;
+          w = qx * qx + qy * qy + qz * qz;
+        }
+        v = mult * w * (re * re + im * im) * norm2;
+      } else {
+        shell = -1;
+      }
     }
-    atomicAdd(&bins[shell], mult * w * (re * re + im * im) * norm2);
+    bin_group(bins, shell, v);
   }
   __syncthreads();
   for (int s = threadIdx.x; s < nshells; s += blockDim.x) partials[static_cast<size_t>(blockIdx.x) * nshells + s] = bins[s];
+}
+
+// out[t][s] = sum over blocks, in block order, of partials[t][block][s] (terms t < gridDim.y).
+__global__ __launch_bounds__(256) void bin_merge_kernel(const double* partials, int blocks, int nshells,
+                                                        double* out) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nshells) return;
+  const size_t t = blockIdx.y;
+  const double* p = partials + t * blocks * nshells + s;
+  double acc = 0.0;
+  for (int b = 0; b < blocks; ++b) acc += p[static_cast<size_t>(b) * nshells];
+  out[t * nshells + s] = acc;
 }
 
 // ------------------------------------------------------------------ energy transfer
@@ -531,41 +599,49 @@ __global__ __launch_bounds__(256) void cross_component_kernel(const double* P, c
 // 0 < kx < nx - kx stand for their mirror too, whose summand is equal). kind 0:
 // sign Re[conj(X) Y]; kind 1: -sign Re[i Y (conj(B_hat) x q)_comp] = -sign Re[conj(B_hat) . (i q x Y e_comp)]
 // summed over comp by the caller, with B_hat the three transforms in Bh. Adds into partials
-// unless first is set.
-__global__ __launch_bounds__(kSpecThreads) void transfer_bin_kernel(int kind, const hipfftDoubleComplex* X,
-                                                                    const hipfftDoubleComplex* Y,
-                                                                    const hipfftDoubleComplex* Bh, int comp,
-                                                                    double sign, int nx, int ny, int nz, int nshells,
-                                                                    double norm2, int first, double* partials) {
+// unless first is set. Binned without atomics, as shell_bin_kernel.
+__global__ __launch_bounds__(kBinThreads) void transfer_bin_kernel(int kind, const hipfftDoubleComplex* X,
+                                                                   const hipfftDoubleComplex* Y,
+                                                                   const hipfftDoubleComplex* Bh, int comp,
+                                                                   double sign, int nx, int ny, int nz, int nshells,
+                                                                   double norm2, int first, double* partials) {
   extern __shared__ double bins[];
   for (int s = threadIdx.x; s < nshells; s += blockDim.x) bins[s] = 0.0;
   __syncthreads();
   const size_t nh = static_cast<size_t>(nz) * ny * (nx / 2 + 1);
   const size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
-  for (size_t k = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; k < nh; k += stride) {
-    int kx, ky, kz;
-    half_index(k, nx, ny, kx, ky, kz);
-    const double fx = kx, fy = signed_freq(ky, ny), fz = signed_freq(kz, nz);
-    const int shell = static_cast<int>(floor(sqrt(fx * fx + fy * fy + fz * fz) + 0.5));
-    if (shell >= nshells) continue;
-    const hipfftDoubleComplex y = Y[k];
-    double v;
-    if (kind == 0) {
-      const hipfftDoubleComplex x = X[k];
-      v = sign * (x.x * y.x + x.y * y.y);
-    } else {
-      const double q[3] = {deriv_q(kx, nx), deriv_q(ky, ny), deriv_q(kz, nz)};
-      const int c = (comp + 1) % 3, d = (comp + 2) % 3;
-      const size_t plane = nh;
-      const hipfftDoubleComplex bc = Bh[c * plane + k], bd = Bh[d * plane + k];
-      // z = (conj(B_hat) x q)_comp = conj(B_c) q_d - conj(B_d) q_c
-      const double zr = bc.x * q[d] - bd.x * q[c];
-      const double zi = -bc.y * q[d] + bd.y * q[c];
-      // -Re[i y z] = Im[y z]
-      v = sign * (y.x * zi + y.y * zr);
+  for (size_t base = static_cast<size_t>(blockIdx.x) * blockDim.x; base < nh; base += stride) {
+    const size_t k = base + threadIdx.x;
+    int shell = -1;
+    double v = 0.0;
+    if (k < nh) {
+      int kx, ky, kz;
+      half_index(k, nx, ny, kx, ky, kz);
+      const double fx = kx, fy = signed_freq(ky, ny), fz = signed_freq(kz, nz);
+      shell = static_cast<int>(floor(sqrt(fx * fx + fy * fy + fz * fz) + 0.5));
+      if (shell < nshells) {
+        const hipfftDoubleComplex y = Y[k];
+        if (kind == 0) {
+          const hipfftDoubleComplex x = X[k];
+          v = sign * (x.x * y.x + x.y * y.y);
+        } else {
+          const double q[3] = {deriv_q(kx, nx), deriv_q(ky, ny), deriv_q(kz, nz)};
+          const int c = (comp + 1) % 3, d = (comp + 2) % 3;
+          const size_t plane = nh;
+          const hipfftDoubleComplex bc = Bh[c * plane + k], bd = Bh[d * plane + k];
+          // z = (conj(B_hat) x q)_comp = conj(B_c) q_d - conj(B_d) q_c
+          const double zr = bc.x * q[d] - bd.x * q[c];
+          const double zi = -bc.y * q[d] + bd.y * q[c];
+          // -Re[i y z] = Im[y z]
+          v = sign * (y.x * zi + y.y * zr);
+        }
+        const double mult = (kx == 0 || 2 * kx == nx) ? 1.0 : 2.0;
+        v = mult * v * norm2;
+      } else {
+        shell = -1;
+      }
     }
-    const double mult = (kx == 0 || 2 * kx == nx) ? 1.0 : 2.0;
-    atomicAdd(&bins[shell], mult * v * norm2);
+    bin_group(bins, shell, v);
   }
   __syncthreads();
   for (int s = threadIdx.x; s < nshells; s += blockDim.x) {
@@ -709,6 +785,24 @@ __global__ void max_field_kernel(const double* b, double b0x, double b0y, double
   if (threadIdx.x == 0) out[blockIdx.x] = sh[0];
 }
 
+// Lattice sound speed c_s = 1/sqrt(3): the flame_reduce guard on max |u|.
+constexpr double kSoundSpeed = 0.57735026918962576;
+
+// The reductions of the current state: block partials into partials (c->red_blocks x FLAME_NRED
+// doubles), merged in a fixed order into out (FLAME_NRED doubles, device). Asynchronous.
+hipError_t launch_reduce(const flame_ctx* c, double* partials, double* out) {
+  hipError_t e = by_storage(c, [&](auto tag) {
+    using S = decltype(tag);
+    hipLaunchKernelGGL(reduce_kernel<S>, dim3(c->red_blocks), dim3(kRedThreads), 0, c->stream, make_aux<S>(c),
+                       partials);
+    return hipGetLastError();
+  });
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(reduce_merge_kernel, dim3(1), dim3(64), 0, c->stream, partials, c->red_blocks,
+                     static_cast<double>(c->n), out);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 namespace flame {
@@ -805,7 +899,8 @@ flame_status flame_init(const flame_params* p, const double* u, const double* b,
     return bail(FLAME_E_HIP);
   }
   c->red_blocks = static_cast<int>(std::min<size_t>(kRedBlocksMax, blocks_for(c->n, kRedThreads)));
-  if (hipMalloc(&c->red_partials, sizeof(double) * FLAME_NRED * std::max(c->red_blocks, 1)) != hipSuccess) {
+  // block partials of the reductions plus one row for their merged results
+  if (hipMalloc(&c->red_partials, sizeof(double) * FLAME_NRED * (std::max(c->red_blocks, 1) + 1)) != hipSuccess) {
     c->err = "hipMalloc of reduction scratch failed";
     return bail(FLAME_E_NOMEM);
   }
@@ -891,34 +986,15 @@ flame_status flame_moments(flame_ctx* c, double* rho, double* u, double* b, doub
 
 flame_status flame_reduce(flame_ctx* c, double* out) {
   if (!c || !out) return c ? fail(c, FLAME_E_INVAL, "out is NULL") : FLAME_E_INVAL;
-  hipError_t e = by_storage(c, [&](auto tag) {
-    using S = decltype(tag);
-    hipLaunchKernelGGL(reduce_kernel<S>, dim3(c->red_blocks), dim3(kRedThreads), 0, c->stream, make_aux<S>(c),
-                       c->red_partials);
-    return hipGetLastError();
-  });
+  // block partials, then the merged results behind them in the same scratch
+  double* merged = c->red_partials + static_cast<size_t>(c->red_blocks) * FLAME_NRED;
+  hipError_t e = launch_reduce(c, c->red_partials, merged);
   if (e != hipSuccess) return fail(c, FLAME_E_HIP, std::string("reduce kernel: ") + hipGetErrorString(e));
-  std::vector<double> host(static_cast<size_t>(c->red_blocks) * FLAME_NRED);
-  FLAME_HIP(c, hipMemcpyAsync(host.data(), c->red_partials, sizeof(double) * FLAME_NRED * c->red_blocks,
-                              hipMemcpyDeviceToHost, c->stream));
+  FLAME_HIP(c, hipMemcpyAsync(out, merged, sizeof(double) * FLAME_NRED, hipMemcpyDeviceToHost, c->stream));
   FLAME_HIP(c, hipStreamSynchronize(c->stream));
-  double acc[FLAME_NRED] = {};
-  for (int blk = 0; blk < c->red_blocks; ++blk)
-    for (int k = 0; k < FLAME_NRED; ++k) {
-      const double v = host[blk * FLAME_NRED + k];
-      acc[k] = (k == 4 || k == 6) ? std::max(acc[k], v) : acc[k] + v;
-    }
-  const double n = static_cast<double>(c->n);
-  out[0] = acc[0] / n;
-  out[1] = acc[1] / n;
-  out[2] = acc[2] / n;
-  out[3] = acc[3] / n;
-  out[4] = acc[4];
-  out[5] = sqrt(acc[5] / n);
-  out[6] = acc[6];
-  out[7] = sqrt(acc[7] / n);
-  for (int k = 8; k < FLAME_NRED; ++k) out[k] = acc[k];
-  if (acc[8] > 0) return fail(c, FLAME_E_NONFINITE, "non-finite populations at " + std::to_string(acc[8]) + " nodes");
+  if (out[8] > 0) return fail(c, FLAME_E_NONFINITE, "non-finite populations at " + std::to_string(out[8]) + " nodes");
+  if (out[6] >= kSoundSpeed)
+    return fail(c, FLAME_E_UNSTABLE, "max |u| = " + std::to_string(out[6]) + " reached the lattice sound speed");
   return FLAME_OK;
 }
 
@@ -952,13 +1028,14 @@ flame_status shell_spectrum(flame_ctx* c, int32_t field, int32_t nshells, int k2
     c->plan_ok = true;
     if (hipfftSetStream(c->plan, c->stream) != HIPFFT_SUCCESS) return fail(c, FLAME_E_HIP, "hipfftSetStream failed");
   }
-  const int blocks = static_cast<int>(std::min<size_t>(1024, blocks_for(nh, kSpecThreads)));
+  const int blocks = static_cast<int>(std::min<size_t>(kBinBlocksMax, blocks_for(nh, kBinThreads)));
   if (!c->spec_partials || c->spec_blocks != blocks || c->spec_nshells < nshells) {
     if (c->spec_partials) FLAME_HIP(c, hipFree(c->spec_partials));
     c->spec_partials = nullptr;
     c->spec_blocks = 0;
     c->spec_nshells = 0;
-    if (hipMalloc(&c->spec_partials, sizeof(double) * blocks * nshells) != hipSuccess) {
+    // block partials plus one row for their merged sums
+    if (hipMalloc(&c->spec_partials, sizeof(double) * (static_cast<size_t>(blocks) + 1) * nshells) != hipSuccess) {
       c->spec_partials = nullptr;
       (void)hipGetLastError();  // clear the allocation error so later launch checks do not see it
       return fail(c, FLAME_E_NOMEM, "spectrum: device workspace");
@@ -966,7 +1043,8 @@ flame_status shell_spectrum(flame_ctx* c, int32_t field, int32_t nshells, int k2
     c->spec_blocks = blocks;
     c->spec_nshells = nshells;
   }
-  std::vector<double> host(static_cast<size_t>(blocks) * nshells);
+  double* merged = c->spec_partials + static_cast<size_t>(blocks) * nshells;
+  std::vector<double> host(static_cast<size_t>(nshells));
   for (int s = 0; s < nshells; ++s) e_k[s] = 0.0;
   const double norm2 = 1.0 / (static_cast<double>(c->n) * static_cast<double>(c->n));
   for (int comp = 0; comp < 3; ++comp) {
@@ -979,16 +1057,20 @@ flame_status shell_spectrum(flame_ctx* c, int32_t field, int32_t nshells, int k2
     if (e != hipSuccess) return fail(c, FLAME_E_HIP, std::string("field kernel: ") + hipGetErrorString(e));
     if (hipfftExecD2Z(c->plan, c->spec_real, static_cast<hipfftDoubleComplex*>(c->spec_cplx)) != HIPFFT_SUCCESS)
       return fail(c, FLAME_E_HIP, "hipfftExecD2Z failed");
-    hipLaunchKernelGGL(shell_bin_kernel, dim3(blocks), dim3(kSpecThreads), sizeof(double) * nshells, c->stream,
+    hipLaunchKernelGGL(shell_bin_kernel, dim3(blocks), dim3(kBinThreads), sizeof(double) * nshells, c->stream,
                        static_cast<const hipfftDoubleComplex*>(c->spec_cplx), nx, ny, nz, nshells, norm2, k2,
                        c->spec_partials);
     e = hipGetLastError();
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(bin_merge_kernel, dim3(blocks_for(static_cast<size_t>(nshells), 256), 1), dim3(256), 0,
+                         c->stream, c->spec_partials, blocks, nshells, merged);
+      e = hipGetLastError();
+    }
     if (e == hipSuccess)
-      e = hipMemcpyAsync(host.data(), c->spec_partials, sizeof(double) * blocks * nshells, hipMemcpyDeviceToHost, c->stream);
+      e = hipMemcpyAsync(host.data(), merged, sizeof(double) * nshells, hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return fail(c, FLAME_E_HIP, std::string("spectrum: ") + hipGetErrorString(e));
-    for (int blk = 0; blk < blocks; ++blk)
-      for (int s = 0; s < nshells; ++s) e_k[s] += host[static_cast<size_t>(blk) * nshells + s];
+    for (int s = 0; s < nshells; ++s) e_k[s] += host[s];
   }
   return FLAME_OK;
 }
@@ -1046,11 +1128,13 @@ flame_status energy_transfer(flame_ctx* c, int32_t nshells, double* t_adv, doubl
     if (hipfftSetStream(c->plan_inv, c->stream) != HIPFFT_SUCCESS)
       return fail(c, FLAME_E_HIP, "hipfftSetStream failed");
   }
-  const int blocks = static_cast<int>(std::min<size_t>(1024, blocks_for(nh, kSpecThreads)));
+  const int blocks = static_cast<int>(std::min<size_t>(kBinBlocksMax, blocks_for(nh, kBinThreads)));
   TransferScratch w(c->stream);
   if (hipMalloc(&w.real, sizeof(double) * 11 * n) != hipSuccess) w.real = nullptr;
   if (w.real && hipMalloc(&w.cplx, sizeof(hipfftDoubleComplex) * 7 * nh) != hipSuccess) w.cplx = nullptr;
-  if (w.cplx && hipMalloc(&w.partials, sizeof(double) * 4 * blocks * nshells) != hipSuccess) w.partials = nullptr;
+  // 4 terms of block partials, then the 4 merged rows
+  if (w.cplx && hipMalloc(&w.partials, sizeof(double) * 4 * (static_cast<size_t>(blocks) + 1) * nshells) != hipSuccess)
+    w.partials = nullptr;
   if (!w.partials) {
     (void)hipGetLastError();  // clear the allocation error so later launch checks do not see it
     return fail(c, FLAME_E_NOMEM, "energy transfer: device workspace");
@@ -1079,7 +1163,7 @@ flame_status energy_transfer(flame_ctx* c, int32_t nshells, double* t_adv, doubl
   };
   const double norm2 = 1.0 / (static_cast<double>(n) * static_cast<double>(n));
   auto bin = [&](int kind, int term, const hipfftDoubleComplex* X, int comp, double sign, bool first) {
-    hipLaunchKernelGGL(transfer_bin_kernel, dim3(blocks), dim3(kSpecThreads), sizeof(double) * nshells, c->stream,
+    hipLaunchKernelGGL(transfer_bin_kernel, dim3(blocks), dim3(kBinThreads), sizeof(double) * nshells, c->stream,
                        kind, X, spec, Bh, comp, sign, nx, ny, nz, nshells, norm2, first ? 1 : 0,
                        w.partials + static_cast<size_t>(term) * blocks * nshells);
     return hipGetLastError() == hipSuccess;
@@ -1112,8 +1196,14 @@ flame_status energy_transfer(flame_ctx* c, int32_t nshells, double* t_adv, doubl
     }
   }
   const int terms = t_hall ? 4 : 3;
-  std::vector<double> host(static_cast<size_t>(terms) * blocks * nshells);
-  if (ok) ok = hipMemcpyAsync(host.data(), w.partials, sizeof(double) * host.size(), hipMemcpyDeviceToHost,
+  double* merged = w.partials + static_cast<size_t>(4) * blocks * nshells;
+  if (ok) {
+    hipLaunchKernelGGL(bin_merge_kernel, dim3(blocks_for(static_cast<size_t>(nshells), 256), terms), dim3(256), 0,
+                       c->stream, w.partials, blocks, nshells, merged);
+    ok = hipGetLastError() == hipSuccess;
+  }
+  std::vector<double> host(static_cast<size_t>(terms) * nshells);
+  if (ok) ok = hipMemcpyAsync(host.data(), merged, sizeof(double) * host.size(), hipMemcpyDeviceToHost,
                               c->stream) == hipSuccess;
   if (ok) ok = hipStreamSynchronize(c->stream) == hipSuccess;
   if (!ok) {
@@ -1122,11 +1212,8 @@ flame_status energy_transfer(flame_ctx* c, int32_t nshells, double* t_adv, doubl
                                     hipGetErrorString(last) + ")");
   }
   double* outs[4] = {t_adv, t_lor, t_ind, t_hall};
-  for (int t = 0; t < terms; ++t) {
-    for (int s = 0; s < nshells; ++s) outs[t][s] = 0.0;
-    for (int blk = 0; blk < blocks; ++blk)
-      for (int s = 0; s < nshells; ++s) outs[t][s] += host[(static_cast<size_t>(t) * blocks + blk) * nshells + s];
-  }
+  for (int t = 0; t < terms; ++t)
+    for (int s = 0; s < nshells; ++s) outs[t][s] = host[static_cast<size_t>(t) * nshells + s];
   return FLAME_OK;
 }
 

@@ -63,6 +63,22 @@ template <typename S>
 __device__ __forceinline__ S ld(const S* base, uint32_t off) {
   return *reinterpret_cast<const S*>(reinterpret_cast<const char*>(base) + off * static_cast<uint32_t>(sizeof(S)));
 }
+// Streaming load: the value is used once and shared with no other workgroup, so it should not
+// displace lines that neighbouring workgroups still read from L2.
+template <typename S>
+__device__ __forceinline__ S ld_stream(const S* base, uint32_t off) {
+  return __builtin_nontemporal_load(
+      reinterpret_cast<const S*>(reinterpret_cast<const char*>(base) + off * static_cast<uint32_t>(sizeof(S))));
+}
+#ifndef FLAME_ZMARCH_STREAM_FLUID
+#define FLAME_ZMARCH_STREAM_FLUID 0
+#endif
+// Stencil kernel: compute the ring of b around the tile one plane ahead, together with the
+// tile's own loads of that plane (the ring nodes' populations are the ones the neighbouring
+// tiles load at about the same time).
+#ifndef FLAME_ZMARCH_RING_AHEAD
+#define FLAME_ZMARCH_RING_AHEAD 0
+#endif
 #ifndef FLAME_NT_STORES
 #define FLAME_NT_STORES 1
 #endif
@@ -86,8 +102,9 @@ struct Planes {
   __device__ __forceinline__ uint32_t at(int dz) const { return p[dz + 1]; }
 };
 
-// Fluid populations of the node. FAA: in place (PAR selects the AA step); else pull.
-template <typename S, bool FAA, int PAR>
+// Fluid populations of the node. FAA: in place (PAR selects the AA step); else pull. STREAM:
+// non-temporal loads.
+template <typename S, bool FAA, int PAR, bool STREAM = false>
 __device__ __forceinline__ void load_fluid(const StepArgs<S>& a, const Rows& rw, const Planes& pl,
                                            typename Enc<S>::R (&f)[kQ]) {
   using E = Enc<S>;
@@ -97,7 +114,7 @@ __device__ __forceinline__ void load_fluid(const StepArgs<S>& a, const Rows& rw,
     const bool own = FAA && PAR == 0;
     const uint32_t off = own ? rw.at(0, 0) + pl.at(0) : rw.at(-cq(i, 0), -cq(i, 1)) + pl.at(-cq(i, 2));
     const S* base = a.f_src + static_cast<size_t>(FAA && PAR == 1 ? oppq(i) : i) * a.stride;
-    f[i] = E::dec(ld(base, off), R(1.0 / E::fscale(i)));
+    f[i] = E::dec(STREAM ? ld_stream(base, off) : ld(base, off), R(1.0 / E::fscale(i)));
   }
 }
 
@@ -331,15 +348,16 @@ __global__ __launch_bounds__(kTX * Tile<typename Enc<S>::R>::ty, FLAME_ZMARCH_WA
   };
 
   R g_next[kM];
+  const Planes p0(z_begin, nz, plane);
   if (active) {
     R gp[kM];
     const Planes pp(wrap(z_begin - 1, nz), nz, plane);
     load_magnetic<S, false, 0>(a, rw, pp, gp);
     put_b(0, gp, rw.at(0, 0) + pp.at(0));
-    const Planes p0(z_begin, nz, plane);
     load_magnetic<S, false, 0>(a, rw, p0, g_next);
     put_b(1, g_next, rw.at(0, 0) + p0.at(0));
   }
+  if (FLAME_ZMARCH_RING_AHEAD) ring(1, p0);
   int prev = 0, cur = 1, next = 2, spare = 3;
   for (int z = z_begin; z < z_end; ++z) {
     R g[kM];
@@ -353,11 +371,14 @@ __global__ __launch_bounds__(kTX * Tile<typename Enc<S>::R>::ty, FLAME_ZMARCH_WA
       load_magnetic<S, false, 0>(a, rw, pn, g_next);
       put_b(next, g_next, rw.at(0, 0) + pn.at(0));
     }
-    ring(cur, pl);
+    if (FLAME_ZMARCH_RING_AHEAD)
+      ring(next, pn);
+    else
+      ring(cur, pl);
     if (active) {
       // the fluid half of the update needs no J: collide and store it before the barrier
       R f[kQ];
-      load_fluid<S, FAA, PAR>(a, rw, pl, f);
+      load_fluid<S, FAA, PAR, FLAME_ZMARCH_STREAM_FLUID != 0>(a, rw, pl, f);
       forcing_at(a, cell, F, Sb);
       if (SAVE) save_state(a.save, a.n, cell, f, g);
       const FluidMoments<R> m = fluid_moments(f);

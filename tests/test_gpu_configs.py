@@ -12,6 +12,7 @@ differences by about e^4 ~ 55 over its ~4 large-eddy turnover times (L/u ~ 500 s
 that for shells 5..8, whose energy the cascade builds during the run. Measured: 7e-5, 2.6e-4
 and 6.6e-5."""
 
+import math
 import os
 
 import pytest
@@ -91,7 +92,8 @@ def test_adjoint_configuration_128():
     of 1e-4 (0.5% of the field rms) leaves an O(eps^2) truncation of order 1e-2, which the run
     prints together with the steps 1e-5 and 1e-6 to show the eps^2 convergence; the bar applies
     at 1e-6, where FP64 rounding of the loss difference is still ~1e-10 of it. The FP32 gradient
-    against the FP64 one (direction and size)."""
+    against the FP64 one (direction and size). All 16 seeded directions are checked; the first
+    two also at 1e-5, and the relative errors at the configured step 1e-4 are printed."""
     from paper_2212_11024_amd.adjoint import RolloutConfig, rollout, shell_spectrum
     from paper_2212_11024_amd.solver import Solver
     n, steps, ckpt, nsh = 128, 1000, 50, 65
@@ -127,17 +129,30 @@ def test_adjoint_configuration_128():
             return float(loss_of(B))
 
     gu64, gb64 = grads["f64"]
-    for j in range(2):
+    rows = []
+    for j in range(16):
         du, _ = synthetic.evaluate(synthetic.shell_field(100 + j, 1, 8, 1.0), shape, "cuda", gradient=False)
         db, _ = synthetic.evaluate(synthetic.shell_field(200 + j, 1, 8, 1.0), shape, "cuda", gradient=False)
         ad = float((gu64 * du).sum() + (gb64 * db).sum())
-        rels = []
-        for eps in (1e-4, 1e-5, 1e-6):
-            fd = (loss_at(du, db, eps) - loss_at(du, db, -eps)) / (2 * eps)
-            rels.append(abs(ad - fd) / abs(fd))
-            print(f"[config4] direction {j}, step {eps:g}: adjoint {ad:.10e} fd {fd:.10e} rel {rels[-1]:.2e}",
-                  flush=True)
-        assert rels[-1] < 1e-4 and rels[-1] < rels[0]
+        fds = {}
+        for eps in ((1e-4, 1e-5, 1e-6) if j < 2 else (1e-4, 1e-6)):
+            fds[eps] = (loss_at(du, db, eps) - loss_at(du, db, -eps)) / (2 * eps)
+            print(f"[config4] direction {j}, step {eps:g}: adjoint {ad:.10e} fd {fds[eps]:.10e} "
+                  f"rel {abs(ad - fds[eps]) / abs(fds[eps]):.2e}", flush=True)
+        rows.append((ad, fds))
+    # relative to each direction's derivative, with a floor of 1% of the largest one so that a
+    # direction nearly orthogonal to the gradient is not judged by its rounding alone
+    floor = 0.01 * max(abs(fds[1e-6]) for _, fds in rows)
+    at_configured, at_fine = [], []
+    for ad, fds in rows:
+        at_configured.append(abs(ad - fds[1e-4]) / max(abs(fds[1e-4]), floor))
+        at_fine.append(abs(ad - fds[1e-6]) / max(abs(fds[1e-6]), floor))
+    print("[config4] relative error at the configured step 1e-4, 16 directions: "
+          + " ".join(f"{r:.1e}" for r in at_configured), flush=True)
+    print("[config4] relative error at the step 1e-6, 16 directions: " + " ".join(f"{r:.1e}" for r in at_fine),
+          flush=True)
+    assert max(at_fine) < 1e-4
+    assert all(f < c for f, c in zip(at_fine, at_configured))
     a = torch.cat([g.reshape(-1) for g in grads["f64"]])
     c = torch.cat([g.reshape(-1) for g in grads["f32"]])
     cos = float((a * c).sum() / (a.norm() * c.norm()))
@@ -146,8 +161,15 @@ def test_adjoint_configuration_128():
     assert cos > 0.999 and rel < 1e-3
 
 
-@pytest.mark.skipif(os.environ.get("FLAME_LARGE") != "1",
-                    reason="1024^3 runs need ~260 GB of HBM and ~2 minutes: set FLAME_LARGE=1")
+def _free_hbm_gb():
+    """Free device memory after releasing what earlier tests left in torch's cache."""
+    import gc
+    gc.collect()
+    torch.cuda.empty_cache()
+    free, _ = torch.cuda.mem_get_info()
+    return free / 1e9
+
+
 def test_large_fp16_1024():
     """The large configuration: 1024^3, FP16 deviation storage with FP32 arithmetic, moment J,
     AA in place (103 GB of populations), decaying turbulence from seeded shells 1..4 (rms 0.02),
@@ -158,9 +180,15 @@ def test_large_fp16_1024():
     throughput of both, the first record with non-finite values (none expected: the moment
     route is stable beyond the whistler CFL bound), FP16 against FP32 shell spectra. Bar on the
     energetic shells 1..4: FP16 rounds each stored deviation to ~4.9e-4 relative per step, a
-    random walk of ~1.1e-2 over 500 steps; measured 3.7e-4 at most (1024^3: FP16 53.5 ms/step,
-    FP32 68.7 ms/step)."""
+    random walk of ~1.1e-2 over 500 steps; measured 3.7e-4 at most (1024^3: FP16 51.5 ms/step,
+    FP32 68.7 ms/step). Skipped only when the device has less free memory than the FP32 run
+    needs."""
     from paper_2212_11024_amd.solver import Solver
+    need = 262.0          # FP32 populations (206 GB) beside u and b (52 GB) at its initialisation
+    free = _free_hbm_gb()
+    print(f"[large] free device memory {free:.1f} GB", flush=True)
+    if free < need:
+        pytest.skip(f"1024^3 needs {need:.0f} GB of free HBM, {free:.0f} GB free")
     n, steps, every, nsh = 1024, 500, 100, 17
     shape = (n, n, n)
     u, _ = synthetic.evaluate(synthetic.shell_field(0, 1, 4, 0.02), shape, "cuda", gradient=False)
@@ -202,3 +230,84 @@ def test_large_fp16_1024():
         rel = (a[1:9] - r[1:9]).abs() / r[1:9]
         print(f"[large] FP16 vs FP32 {f}, shells 1..8: " + " ".join(f"{float(x):.1e}" for x in rel), flush=True)
         assert float(rel[:4].max()) < 1e-2
+
+
+def _forced_512(storage, d_i, steps, every, nsh=33):
+    """The forced-turbulence workload at 512^3 (moment J, AA): reductions and shell spectra every
+    `every` steps; the first step count whose reductions show a blown-up state (non-finite
+    populations or max|u| at the sound speed) ends the run."""
+    import bench
+    s = bench.make_solver(512, storage, "moment", "aa", d_i=d_i)
+    records, ms, first_bad = [], 0.0, None
+    for k in range(steps // every):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        s.step(every)
+        e1.record()
+        torch.cuda.synchronize()
+        ms += e0.elapsed_time(e1)
+        red = s.reduce(allow_nonfinite=True)
+        bad = int(red[8]) > 0 or float(red[6]) >= 3 ** -0.5
+        records.append((s.steps, red, None if bad else (s.spectrum("u", nsh), s.spectrum("B", nsh))))
+        print(f"[config3] {storage} d_i={d_i:g} step {s.steps}: E_kin {float(red[0]):.6e} E_mag {float(red[1]):.6e} "
+              f"max|u| {float(red[6]):.4f} non-finite {int(red[8])}", flush=True)
+        if bad:
+            first_bad = s.steps
+            break
+    taken = s.steps
+    s.close()
+    torch.cuda.empty_cache()
+    print(f"[config3] {storage} d_i={d_i:g}: {ms / max(taken, 1):.3f} ms/step, "
+          f"first blown-up record: {first_bad}", flush=True)
+    return records, first_bad
+
+
+def test_forced_512_fp32_tracks_fp64_over_5000_steps():
+    """The forced configuration as configured: 512^3, FP32 deviation storage against an FP64 run of
+    the same workload (nu = eta = 0.001, d_i = 4, static forcing at |k| <= 2), 5000 steps, shell
+    spectra of u and B every 1000 steps. Both runs stay finite and below the sound speed; FP32
+    tracks FP64 shell by shell. The static forcing keeps feeding the flow (its kinetic energy grows
+    fourfold and max|u| reaches 0.3-0.4 by step 5000), which turns chaotic: from step ~2000 the two
+    runs decorrelate at the largest scales, whatever the storage precision, and the error of the
+    shell energies stops growing at ~2% (measured: 8.4e-4 / 2.0e-3 on shells 1..8 at step 1000,
+    then 1.7e-2 / 1.2e-2 for u / B at step 5000; energy-weighted 4.4e-3). The bars (5e-2 on shells
+    1..8, 1e-2 energy-weighted) sit above that saturation: they catch a systematic FP32 drift or a
+    broken run, not the chaos of the flow."""
+    print("[config3] 512^3 forced, d_i = 4, 5000 steps, FP64 then FP32", flush=True)
+    runs = {st: _forced_512(st, 4.0, 5000, 1000) for st in ("f64", "f32")}
+    for st, (_, bad) in runs.items():
+        assert bad is None, (st, bad)
+    worst_rel, worst_w = 0.0, 0.0
+    for (t, _, s64), (_, _, s32) in zip(runs["f64"][0], runs["f32"][0]):
+        line = []
+        for a, r in zip(s32, s64):
+            rel = float(((a[1:9] - r[1:9]).abs() / r[1:9]).max())
+            w = float((a[1:] - r[1:]).abs().sum() / r[1:].sum())
+            worst_rel, worst_w = max(worst_rel, rel), max(worst_w, w)
+            line.append(f"{rel:.2e} / {w:.2e}")
+        print(f"[config3] step {t}: FP32 vs FP64 shells 1..8 max rel / weighted 1..32: u {line[0]}, B {line[1]}",
+              flush=True)
+    assert worst_rel < 5e-2 and worst_w < 1e-2, (worst_rel, worst_w)
+
+
+def test_forced_512_hall_transition():
+    """The MHD to Hall-MHD transition of the forced configuration at the other two Hall parameters,
+    d_i = 0 (ideal MHD) and d_i = 16 (whistler CFL number ~2.6 at the initial max|B|: the survey
+    expects a possible blow-up), FP32, 5000 steps, reductions every 250 steps. Reported: the step of
+    the first blown-up record, if any. Checked: ideal MHD stays finite; d_i = 16 either stays finite
+    or its blow-up is detected by flame_reduce (FLAME_E_NONFINITE / FLAME_E_UNSTABLE) rather than
+    passing silently."""
+    from paper_2212_11024_amd import _lib as L
+    out = {}
+    for d_i in (0.0, 16.0):
+        records, bad = _forced_512("f32", d_i, 5000, 250, nsh=17)
+        out[d_i] = (records, bad)
+    assert out[0.0][1] is None
+    records, bad = out[16.0]
+    print(f"[config3] d_i = 16: first blown-up record at step {bad}", flush=True)
+    if bad is not None:
+        red = records[-1][1]
+        assert int(red[8]) > 0 or float(red[6]) >= 3 ** -0.5
+    else:
+        e = [float(r[1][0] + r[1][1]) for r in records]
+        assert all(math.isfinite(x) for x in e)

@@ -119,6 +119,74 @@ def test_run_to_run_determinism():
     assert torch.equal(a.reduce(), b.reduce())
 
 
+@pytest.mark.parametrize("shape", [(13, 10, 9), (48, 40, 36)])
+def test_spectra_are_bitwise_reproducible(shape):
+    """Shell spectra, dissipation spectra and the energy-transfer terms sum in a fixed order (no
+    atomics): two runs from the same inputs, and two calls on one state, agree bit for bit. The
+    larger grid spreads the half spectrum over many binning blocks and puts many lanes of a
+    wavefront into one shell."""
+    case = Case(*shape, jmode="stencil", forced=True, seed=31, kmax=3)
+    _print_case("spectra determinism", shape=shape)
+    runs = []
+    for _ in range(2):
+        s = gpu_solver(case, "f64", "aa")
+        s.step(5)
+        ns = max(shape) // 2 + 1
+        out = [s.spectrum("u", ns), s.spectrum("B", ns), s.dissipation_spectrum("u", ns),
+               s.dissipation_spectrum("B", ns), s.energy_transfer(ns, hall=True)]
+        again = [s.spectrum("u", ns), s.spectrum("B", ns), s.dissipation_spectrum("u", ns),
+                 s.dissipation_spectrum("B", ns), s.energy_transfer(ns, hall=True)]
+        for x, y in zip(out, again):
+            assert torch.equal(x, y)
+        runs.append(out)
+        s.close()
+    for x, y in zip(*runs):
+        assert torch.equal(x, y)
+        assert bool(torch.isfinite(x).all())
+
+
+def test_unstable_state_is_reported():
+    """flame_reduce returns FLAME_E_UNSTABLE (after filling its slots) once max |u| reaches the
+    lattice sound speed 1/sqrt(3), and FLAME_OK below it. The states are set from the host: mass
+    moved from the rest population to the +x one gives a uniform flow u_x = m at rho = 1."""
+    from paper_2212_11024_amd import _lib as L
+    case = CASES["ragged_moment"]
+    s = gpu_solver(case, "f64", "aa")
+    rest_f, rest_g = s.rest_populations()
+    shape = (case.nz, case.ny, case.nx)
+    plus_x = 14                          # c = (1, 0, 0) in the App. A order
+    for m, expect in ((0.5, L.FLAME_OK), (0.7, L.FLAME_E_UNSTABLE)):
+        f = rest_f.view(27, 1, 1, 1).expand(27, *shape).clone()
+        f[0] -= m
+        f[plus_x] += m
+        g = rest_g.view(7, 3, 1, 1, 1).expand(7, 3, *shape).clone()
+        s.set_populations(f, g)
+        code, vals = L.flame_reduce(s.ctx, allow_nonfinite=True)
+        assert code == expect, (m, code, L.flame_last_error(s.ctx))
+        assert abs(vals[6] - m) < 1e-12 and vals[8] == 0
+        if expect != L.FLAME_OK:
+            with pytest.raises(L.FlameError) as e:
+                s.reduce()
+            assert e.value.code == L.FLAME_E_UNSTABLE
+    s.close()
+
+
+def test_whistler_cfl_warning():
+    """flame_init returns the warning FLAME_W_CFL (and a usable context) when the advisory whistler
+    number pi d_i max|B| of the initial field exceeds 1, FLAME_OK otherwise (Sec. 3.4)."""
+    from paper_2212_11024_amd import _lib as L
+    for d_i, expect in ((0.5, L.FLAME_OK), (8.0, L.FLAME_W_CFL)):
+        case = Case(9, 8, 7, jmode="moment", d_i=d_i, b0=(0.0, 0.0, 0.1), seed=17)
+        s = gpu_solver(case, "f32", "aa")
+        _, _, b, _, _, _ = inputs(case)
+        bmax = float(((b + torch.tensor(case.b0, dtype=b.dtype).view(3, 1, 1, 1)) ** 2).sum(0).sqrt().max())
+        assert abs(s.cfl - math.pi * d_i * bmax) <= 1e-12 * s.cfl
+        assert s.status == expect, (d_i, s.cfl, s.status)
+        s.step(3)
+        assert int(s.reduce()[8]) == 0
+        s.close()
+
+
 def test_set_get_roundtrip_and_resume():
     case = CASES["ragged_moment"]
     _print_case("resume")

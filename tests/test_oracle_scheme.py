@@ -13,7 +13,19 @@ import synthetic
 from oracle import analytic, diagnostics, scheme
 from oracle.lattice import C, C2, CS2
 
-TOL_WAVE = {"stencil": 0.01, "moment": 0.05}
+# Bars on the relative L2 error of u and of b - b0 against the exact wave at 32 nodes per
+# wavelength after 200 steps (b0 = 0.1, amplitude 1e-3, nu = eta = 0.01, d_i = 2), per J route and
+# branch: the measured error times 1.25 (moment route on beta-: 1.16, the bar it had before).
+# Measured (u, b): moment beta+ 2.92% / 4.01%, beta- 8.86% / 10.76%; stencil beta+ 0.39% / 0.61%,
+# beta- 0.57% / 0.58%. The moment route's error is a phase lag (test_wave_error_is_a_phase_error):
+# its frequency is off by 1.06% (beta+) and 2.15% (beta-), the scheme's second-order dispersion
+# error at this resolution (Sec. 4.3: it falls as N^-2), which builds up to 0.03 and 0.09 rad of
+# phase over the 200 steps (omega t = 3.2 and 4.8 rad).
+TOL_WAVE = {("moment", +1): 0.050, ("moment", -1): 0.125, ("stencil", +1): 0.0076, ("stencil", -1): 0.0073}
+# the same wave with the BGK fluid collision (measured moment 4.06%, stencil 0.66%, times 1.25)
+TOL_WAVE_BGK = {"moment": 0.051, "stencil": 0.0083}
+# the electron-MHD whistler at 32 nodes per wavelength (measured moment 1.26%, stencil 0.87%, times 1.25)
+TOL_WAVE_EMHD = {"moment": 0.016, "stencil": 0.011}
 
 
 def _wave_run(N, steps, amp, b0, d_i, nu=0.01, branch=+1, jmode="stencil", nx=1, ny=1,
@@ -43,8 +55,45 @@ def _wave_error(N, steps, amp, b0, d_i, **kw):
 def test_exact_hall_wave(jmode, branch):
     # 32 nodes per wavelength, b0 = 0.1, amplitude 1e-3, nu = eta = 0.01, d_i = 2, 200 steps
     eu, eb = _wave_error(32, 200, 1e-3, 0.1, 2.0, branch=branch, jmode=jmode)
-    tol = TOL_WAVE[jmode] * (1.0 if branch > 0 else 2.5)
+    tol = TOL_WAVE[(jmode, branch)]
     assert eu < tol and eb < tol, (eu, eb)
+
+
+def _mode_amplitude(v, k):
+    """Complex amplitude of the circularly polarised mode: mean over z of (v_y + i v_x) e^{-ikz}
+    (the exact wave's is a e^{-nu k^2 t} e^{-i w t})."""
+    z = torch.arange(v.shape[1], dtype=torch.float64)
+    return complex(((v[1] + 1j * v[0]) * torch.exp(-1j * k * z)).mean())
+
+
+@pytest.mark.parametrize("branch", [+1, -1])
+def test_wave_error_is_a_phase_error(branch):
+    """The moment route's larger exact-wave error is a phase lag from its frequency error, the
+    dispersion error of Sec. 4.3 (second order in the grid spacing), not an amplitude error: the
+    numerical mode amplitude against the exact one after 200 steps has a phase offset that makes
+    up nearly all of the L2 error, and the phase offset grows linearly in time at a relative
+    frequency error of 1.06% (beta+) / 2.15% (beta-) (bars x1.25). The stencil route's frequency
+    error is below 0.2% on both branches."""
+    N, b0, amp, d_i = 32, 0.1, 1e-3, 2.0
+    k = 2 * math.pi / N
+    w = analytic.frequency(d_i, k, b0, branch)
+    bars = {"moment": 0.0106 if branch > 0 else 0.0215, "stencil": 0.0014 if branch > 0 else 0.0009}
+    for jmode in ("moment", "stencil"):
+        times, phases = [], []
+        p, st = _wave_run(N, 0, amp, b0, d_i, branch=branch, jmode=jmode)
+        for t in range(40, 201, 40):
+            st = scheme.step(st, p, 40)
+            _, U, _, _, _ = scheme.fields(st, p)
+            ue, _ = analytic.wave(N, t, amp, b0, p.nu, d_i, branch)
+            r = _mode_amplitude(U[:, :, 0, 0], k) / _mode_amplitude(ue, k)
+            times.append(t)
+            phases.append(math.atan2(r.imag, r.real))
+        rel_freq = abs(np.polyfit(times, phases, 1)[0] / w)
+        eu = float(torch.linalg.norm(U[:, :, 0, 0] - ue) / torch.linalg.norm(ue))
+        assert rel_freq < 1.25 * bars[jmode], (jmode, rel_freq)
+        if jmode == "moment":
+            assert rel_freq > 0.75 * bars[jmode], rel_freq                  # the reading, not just a bound
+            assert abs(abs(r) - 1.0) < 0.25 * eu and abs(phases[-1]) > 0.95 * eu, (abs(r), phases[-1], eu)
 
 
 @pytest.mark.parametrize("jmode", ["stencil", "moment"])
@@ -66,7 +115,7 @@ def test_exact_hall_wave_bgk_fluid(jmode):
     # the BGK fluid variant (S = omega I) carries the same Navier-Stokes viscosity: the same
     # exact wave and bound as the central-moment collision
     eu, eb = _wave_error(32, 200, 1e-3, 0.1, 2.0, jmode=jmode, collision="bgk")
-    assert eu < TOL_WAVE[jmode] and eb < TOL_WAVE[jmode], (eu, eb)
+    assert eu < TOL_WAVE_BGK[jmode] and eb < TOL_WAVE_BGK[jmode], (eu, eb)
 
 
 def _emhd_error(N, steps, amp, b0, d_i, jmode, eta=0.01):
@@ -93,7 +142,7 @@ def test_exact_emhd_whistler_second_order(jmode):
         s = N / 32
         errs.append(_emhd_error(N, int(round(200 * s * s)), 1e-3 / s, 0.1 / s, 2.0 * s, jmode))
     slope = np.polyfit(np.log(Ns), np.log(errs), 1)[0]
-    assert errs[1] < TOL_WAVE[jmode] and slope < -1.8, (errs, slope)
+    assert errs[1] < TOL_WAVE_EMHD[jmode] and slope < -1.8, (errs, slope)
 
 
 def test_translation_invariance():
