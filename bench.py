@@ -78,30 +78,37 @@ PHYS = dict(nu=0.001, eta=0.001, d_i=4.0, b0=(0.0, 0.0, 0.0))
 
 
 def make_solver(n, storage="f32", jmode="moment", layout="aa", device="cuda", fields=None, d_i=None,
-                collision="central", magnetic="hall", placement_trials=1):
+                collision="central", magnetic="hall", placement_trials=1, fluid_lattice="d3q27",
+                magnetic_lattice="d3q7"):
     import torch
     from paper_2212_11024_amd.solver import Solver
     u, gu, b, gb, fu, fb = fields if fields is not None else workload_fields(n, device)
     s = Solver(n, n, n, PHYS["nu"], PHYS["eta"], PHYS["d_i"] if d_i is None else d_i, PHYS["b0"], storage, jmode,
                layout, u, b, gu, gb, fu, fb, device=device, collision=collision, magnetic=magnetic,
-               placement_trials=placement_trials)
+               placement_trials=placement_trials, fluid_lattice=fluid_lattice, magnetic_lattice=magnetic_lattice)
     torch.cuda.synchronize()
     return s
 
 
-def bytes_per_node(storage, forced=True):
-    """Algorithmic HBM bytes per node update: read and write 27 + 21 populations, plus the
-    static forcing fields (3 + 3 values in the arithmetic type) when forced."""
+LATTICE_VALUES = {"d3q27": 27, "d3q19": 19, "d3q7": 21, "d3q15": 45}
+
+
+def bytes_per_node(storage, forced=True, fluid_lattice="d3q27", magnetic_lattice="d3q7"):
+    """Algorithmic HBM bytes per node update: read and write every population (27 + 21 on the
+    paper's velocity sets; q + 3 m on the lattice variants), plus the static forcing fields
+    (3 + 3 values in the arithmetic type) when forced."""
     vb = {"f64": 8, "f32": 4, "f16": 2}[storage]
     fb = 8 if storage == "f64" else 4
-    return 2 * 48 * vb + (6 * fb if forced else 0)
+    pops = LATTICE_VALUES[fluid_lattice] + (81 if magnetic_lattice == "d3q27" else LATTICE_VALUES[magnetic_lattice])
+    return 2 * pops * vb + (6 * fb if forced else 0)
 
 
 def time_variant(n, storage, jmode, d_i, steps, warmup, fields, collision="central", magnetic="hall",
-                 placement_trials=1):
+                 placement_trials=1, fluid_lattice="d3q27", magnetic_lattice="d3q7"):
     import torch
     s = make_solver(n, storage, jmode, "aa", fields=fields, d_i=d_i, collision=collision, magnetic=magnetic,
-                    placement_trials=placement_trials)
+                    placement_trials=placement_trials, fluid_lattice=fluid_lattice,
+                    magnetic_lattice=magnetic_lattice)
     placement = s.placement_ms
     s.step(warmup)
     torch.cuda.synchronize()
@@ -121,9 +128,10 @@ def time_variant(n, storage, jmode, d_i, steps, warmup, fields, collision="centr
     del s
     torch.cuda.empty_cache()
     nodes = n ** 3
-    bpn = bytes_per_node(storage)
+    bpn = bytes_per_node(storage, True, fluid_lattice, magnetic_lattice)
     return {
         "storage": storage, "jmode": jmode, "d_i": d_i, "collision": collision, "magnetic": magnetic,
+        "fluid_lattice": fluid_lattice, "magnetic_lattice": magnetic_lattice,
         "ms_per_step": ms, "wall_s": wall,
         "mlups": nodes / (ms * 1e-3) / 1e6,
         "bytes_per_node": bpn,
@@ -508,13 +516,18 @@ def main(argv=None):
                     # the other two Hall parameters of the forced configuration (MHD to Hall-MHD)
                     ("f32", "moment", 0.0), ("f32", "moment", 16.0),
                     # model variants of the same workload: BGK fluid collision, electron MHD
-                    ("f32", "moment", d_i, "bgk", "hall"), ("f32", "moment", d_i, "central", "emhd")] + variants
+                    ("f32", "moment", d_i, "bgk", "hall"), ("f32", "moment", d_i, "central", "emhd"),
+                    # velocity-set variants: D3Q19 fluid (BGK), D3Q15 and D3Q27 magnetic
+                    ("f32", "moment", d_i, "bgk", "hall", "d3q19", "d3q7"),
+                    ("f32", "moment", d_i, "central", "hall", "d3q27", "d3q15"),
+                    ("f32", "moment", d_i, "central", "hall", "d3q27", "d3q27")] + variants
     results = []
     for storage, jmode, di, *model in variants:
-        coll, mag = model or ("central", "hall")
-        print(f"[bench] {n}^3 {storage} {jmode} d_i={di} {coll} {mag}: {args.warmup} warm-up + {args.steps} "
+        coll, mag, fl, ml = (list(model) + ["central", "hall", "d3q27", "d3q7"][len(model):])
+        print(f"[bench] {n}^3 {storage} {jmode} d_i={di} {coll} {mag} {fl}/{ml}: {args.warmup} warm-up + {args.steps} "
               "timed steps", file=sys.stderr, flush=True)
-        r = time_variant(n, storage, jmode, di, args.steps, args.warmup, fields, coll, mag, args.placement_trials)
+        r = time_variant(n, storage, jmode, di, args.steps, args.warmup, fields, coll, mag, args.placement_trials,
+                         fl, ml)
         print(f"[bench]   {r['ms_per_step']:.3f} ms/step, {r['mlups']:.0f} MLUPS, {r['achieved_GBps']:.0f} GB/s, "
               f"non-finite nodes {r['nonfinite_nodes']}", file=sys.stderr, flush=True)
         results.append(r)
@@ -522,11 +535,11 @@ def main(argv=None):
         results = results[-1:] + results[:-1]          # the headline first in the report
     del fields
     torch.cuda.empty_cache()
-    ref = {(r["jmode"], r["d_i"], r["collision"], r["magnetic"]): r["_spectra"] for r in results
-           if r["storage"] == "f64"}
+    ref = {(r["jmode"], r["d_i"], r["collision"], r["magnetic"], r["fluid_lattice"], r["magnetic_lattice"]):
+           r["_spectra"] for r in results if r["storage"] == "f64"}
     for r in results:
         sp = r.pop("_spectra")
-        key = (r["jmode"], r["d_i"], r["collision"], r["magnetic"])
+        key = (r["jmode"], r["d_i"], r["collision"], r["magnetic"], r["fluid_lattice"], r["magnetic_lattice"])
         if r["storage"] != "f64" and key in ref:
             err = spectral_error(sp, ref[key])
             r["spectral_error_vs_f64"] = {f: {k: sig(v) for k, v in e.items()} for f, e in err.items()}
@@ -552,6 +565,7 @@ def main(argv=None):
     def traffic_of(r):
         rec = TRAFFIC_RECORDS.get((r["storage"], r["jmode"]))
         if (n == 512 and rec and (r["collision"], r["magnetic"]) == ("central", "hall") and r["d_i"] == d_i
+                and (r["fluid_lattice"], r["magnetic_lattice"]) == ("d3q27", "d3q7")
                 and kernel_fingerprint() == rec["fingerprint"]):
             return rec["GB_per_launch"]
         return None
@@ -573,8 +587,9 @@ def main(argv=None):
                 "algorithmic_GB_per_launch": round(r["bytes_per_node"] * n ** 3 / 1e9, 3),
                 "bytes_per_node": r["bytes_per_node"], "placement_trial_frac": placement_spread(r)}
 
-    f64_head = next((r for r in results if (r["storage"], r["jmode"], r["d_i"], r["collision"], r["magnetic"])
-                     == ("f64", "moment", d_i, "central", "hall")), None)
+    f64_head = next((r for r in results if (r["storage"], r["jmode"], r["d_i"], r["collision"], r["magnetic"],
+                                             r["fluid_lattice"], r["magnetic_lattice"])
+                     == ("f64", "moment", d_i, "central", "hall", "d3q27", "d3q7")), None)
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)

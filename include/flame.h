@@ -22,7 +22,8 @@
  *     directions rest, -x, -y, -z, +x, +y, +z, each with components x, y, z.
  *     A canonical population array is double [27][nz][ny][nx] followed by
  *     double [7][3][nz][ny][nx] (48 * ncell doubles), holding the post-streaming,
- *     pre-collision values of the current time (full values, not deviations).
+ *     pre-collision values of the current time (full values, not deviations). On the lattice
+ *     variants (FLAME_FLUID_*, FLAME_MAGNETIC_* below) it is [q][...] then [m][3][...].
  *   - Vector fields are double [3][nz][ny][nx]; gradients double [3][3][nz][ny][nx] with
  *     grad[a][b] = d field_b / d x_a.
  *   - "device" pointers are HIP device memory of the device current when flame_init was
@@ -34,6 +35,10 @@
  *   - Status codes: 0 OK, negative = error (nothing was enqueued unless stated),
  *     positive = warning flags (the call completed).
  *   - A context is not thread-safe; calls on one context must not overlap.
+ *   - Launch-shape tuning, read from the environment by flame_init (results do not depend on
+ *     it, bitwise): FLAME_ZCHUNK_PLANES = planes per workgroup of the curl-stencil kernel
+ *     (default 32), FLAME_ROW_THREADS = threads per row block of the node-local kernels, a
+ *     multiple of 64 (default: the row rounded up to whole wavefronts, at most 256).
  */
 #ifndef FLAME_H
 #define FLAME_H
@@ -88,6 +93,28 @@ typedef int32_t flame_status;
 #define FLAME_MAGNETIC_HALL 0
 #define FLAME_MAGNETIC_EMHD 1
 
+/* Velocity sets (the lattice figure of Sec. 3.1; Sec. 4.3 reports runs with the larger magnetic
+ * sets). The paper's are D3Q27 for the fluid and D3Q7 for the magnetic field (0, the defaults).
+ * D3Q19 fluid: the App. A listing without its eight corners (directions 0..9 and 14..22 of it),
+ *   weights 1/3, 1/18, 1/36; it runs the BGK collision (FLAME_COLLISION_BGK) towards the
+ *   second-order Hermite equilibrium with the Maxwell-stress term, a body force entering as the
+ *   second-order form w_i [(c_i - U)/c_s^2 + (c_i . U) c_i / c_s^4] . F of the D3Q27 force term.
+ * D3Q15 / D3Q27 magnetic: W = 5/12, 1/12 (faces), 1/96 (corners), resp. 17/36, 1/18, 1/72
+ *   (edges), 1/288 (corners): the fluid weights of the same velocities with the moving ones scaled
+ *   by C^2 / c_s^2 = 3/4, which keeps sum W xi xi = C^2 I with C^2 = 1/4 (node coincidence,
+ *   Sec. 3.2) and fourth-order isotropy. D3Q15 order: rest, -x, -y, -z, (-1,-1,-1), (-1,-1,1),
+ *   (-1,1,-1), (-1,1,1), then the opposites of those seven in the same order; magnetic D3Q27
+ *   takes the App. A order.
+ * The lattice variants run the moment route of J (FLAME_J_MOMENT) in either layout, forward
+ * only (the reverse-mode and trace entry points return FLAME_E_UNSUPPORTED). A canonical
+ * population array then holds q fluid and m x 3 magnetic arrays (q = 27 or 19, m = 7, 15 or 27)
+ * in the orders above. */
+#define FLAME_FLUID_D3Q27 0
+#define FLAME_FLUID_D3Q19 1
+#define FLAME_MAGNETIC_D3Q7 0
+#define FLAME_MAGNETIC_D3Q15 1
+#define FLAME_MAGNETIC_D3Q27 2
+
 /* Reduction slots of flame_reduce (FP64):
  *  0 E_kin = 1/2 <|u|^2>        1 E_mag = 1/2 <|B - b0|^2>     2 H_c = <u . (B - b0)>
  *  3 <|J|^2>                    4 max |div B|                  5 rms div B
@@ -117,18 +144,23 @@ typedef struct {
   int32_t collision;    /* FLAME_COLLISION_CENTRAL (0, the paper's) / FLAME_COLLISION_BGK */
   int32_t magnetic;     /* FLAME_MAGNETIC_HALL (0, the paper's) / FLAME_MAGNETIC_EMHD; the reverse-mode
                            and trace entry points accept only the defaults (FLAME_E_UNSUPPORTED) */
+  int32_t fluid_lattice;     /* FLAME_FLUID_D3Q27 (0, the paper's) / FLAME_FLUID_D3Q19 */
+  int32_t magnetic_lattice;  /* FLAME_MAGNETIC_D3Q7 (0, the paper's) / _D3Q15 / _D3Q27 */
 } flame_params;
 
 typedef struct flame_ctx flame_ctx;
 
 /* Bytes of population storage the caller must provide for these parameters (0 if the
  * parameters are invalid). AB: 96 values per node; AA: 48 (69 with FLAME_J_STENCIL);
- * values are 8, 4 or 2 bytes. */
+ * values are 8, 4 or 2 bytes. On lattice variants: q + 3 m values per node (AA), twice that (AB).
+ * FLAME_E_UNSUPPORTED combinations (a lattice variant with the stencil route, D3Q19 with the
+ * central-moment collision) give 0 as well. */
 size_t flame_storage_bytes(const flame_params* p);
 
 /* Rest state the stored deviations are measured from (host, no device use):
- * f_rest[27] = f^mhd(0)(1, 0, b0) (App. A equilibrium with the Maxwell stress of b0) and
- * g_rest[21] = W_i b0 (index i * 3 + component). Either pointer may be NULL. */
+ * f_rest[q] = f^mhd(0)(1, 0, b0) (App. A equilibrium with the Maxwell stress of b0) and
+ * g_rest[3 m] = W_i b0 (index i * 3 + component); q = 27, m = 7 on the paper's lattices. Either
+ * pointer may be NULL. */
 flame_status flame_rest_populations(const flame_params* p, double* f_rest, double* g_rest);
 
 /* Create a context over caller-owned population storage and fill it with the initial state
@@ -206,7 +238,8 @@ flame_status flame_dissipation_spectrum(flame_ctx* c, int32_t field, int32_t nsh
 flame_status flame_energy_transfer(flame_ctx* c, int32_t nshells, double* t_adv, double* t_lor, double* t_ind,
                                    double* t_hall);
 
-/* Copy the state in canonical order to / from device double dst/src [48 * ncell].
+/* Copy the state in canonical order to / from device double dst/src [48 * ncell]
+ * ([(q + 3 m) * ncell] on lattice variants).
  * deviations = 0: full population values; deviations = 1: departures from the rest state of
  * flame_rest_populations, which are the stored values exactly (decoded), so a get / set pair
  * with deviations = 1 restores a bitwise-identical state (checkpoint / resume).
@@ -216,7 +249,8 @@ flame_status flame_get_populations(flame_ctx* c, double* dst, int32_t deviations
 flame_status flame_set_populations(flame_ctx* c, const double* src, int32_t deviations);
 
 /* Canonical populations of n given nodes: cells (device int64 [n], linear node indices)
- * -> out (device double [n][48]: 27 fluid then 7 x 3 magnetic; full values or deviations as
+ * -> out (device double [n][48]: 27 fluid then 7 x 3 magnetic ([n][q + 3 m] on lattice
+ * variants); full values or deviations as
  * above; NaN rows for indices outside the grid). Asynchronous. */
 flame_status flame_gather(flame_ctx* c, const int64_t* cells, int64_t n, double* out,
                           int32_t deviations);
@@ -242,7 +276,8 @@ flame_status flame_adjoint_step(flame_ctx* c, const void* state, const void* lam
  * source, 48 arrays [q][n] of the storage type (27 fluid, then 7 x 3 magnetic), node stride
  * n = nx*ny*nz, with the stored encoding of the deviations; slot q at node y holds the
  * post-collision population q of node y, so population q of node x at the next step is slot q
- * at x - c_q. flame_trace_bytes(c) bytes each (0 if c is NULL). flame_trace_export writes the
+ * at x - c_q. flame_trace_bytes(c) bytes each (0 if c is NULL or runs a model or velocity-set
+ * variant, which have no trace lattice). flame_trace_export writes the
  * current state (exact: stored values are moved, not recoded); flame_trace_step advances a
  * lattice src by one step into dst (dst must not alias src) without touching the context, and
  * reproduces the context's own steps bitwise. Other routes and layouts (the stencil route, the AB

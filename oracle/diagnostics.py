@@ -145,3 +145,26 @@ def energy_transfer(U, B, J, nshells, d_i=None):
 def max_shell(shape):
     nz, ny, nx = shape
     return int(math.floor(math.sqrt((nz // 2) ** 2 + (ny // 2) ** 2 + (nx // 2) ** 2) + 0.5)) + 1
+
+
+def turbulence_summary(U, B, nu, eta, b0=(0.0, 0.0, 0.0), nshells=None):
+    """Mean-flow quantities of the paper's turbulence runs (Sec. 4.4) from node fields U, B
+    (3, nz, ny, nx): E_kin = 1/2 <|u|^2>, E_mag = 1/2 <|B - b0|^2>, the dissipation rate
+    eps = nu <|grad u|^2> + eta <|grad B|^2> (sums of the dissipation spectra), U = the r.m.s.
+    velocity <|u|^2>^(1/2), the integral length L = 2 pi int E_u(k)/k dk / int E_u(k) dk over
+    shells k = 1..nshells-1 with the box of n cells taken as 2 pi (so L in cells is
+    n sum_k E_u(k)/k / sum_k E_u(k), n the largest axis), and Re = U L / nu."""
+    arr = U.detach().cpu().numpy() if torch.is_tensor(U) else np.asarray(U)
+    barr = B.detach().cpu().numpy() if torch.is_tensor(B) else np.asarray(B)
+    n = max(arr.shape[1:])
+    nshells = nshells or n // 2 + 1
+    e_kin = 0.5 * float((arr ** 2).sum(0).mean())
+    bf = barr - np.asarray(b0, dtype=np.float64).reshape(3, 1, 1, 1)
+    e_mag = 0.5 * float((bf ** 2).sum(0).mean())
+    eps = nu * float(dissipation_spectrum(arr, nshells).sum()) + eta * float(dissipation_spectrum(barr, nshells).sum())
+    eu = spectrum(arr, nshells)[1:]
+    k = np.arange(1, nshells, dtype=np.float64)
+    scale = n * float((eu / k).sum() / eu.sum()) if eu.sum() > 0 else 0.0
+    u_rms = math.sqrt(2.0 * e_kin)
+    return {"E_kin": e_kin, "E_mag": e_mag, "eps": eps, "u_rms": u_rms, "integral_scale": scale,
+            "Re": u_rms * scale / nu}

@@ -26,7 +26,12 @@ FLAME_J_MOMENT, FLAME_J_STENCIL = 0, 1
 FLAME_LAYOUT_AB, FLAME_LAYOUT_AA = 0, 1
 FLAME_COLLISION_CENTRAL, FLAME_COLLISION_BGK = 0, 1
 FLAME_MAGNETIC_HALL, FLAME_MAGNETIC_EMHD = 0, 1
+FLAME_FLUID_D3Q27, FLAME_FLUID_D3Q19 = 0, 1
+FLAME_MAGNETIC_D3Q7, FLAME_MAGNETIC_D3Q15, FLAME_MAGNETIC_D3Q27 = 0, 1, 2
 FLAME_NRED = 16
+
+FLUID_COUNT = {FLAME_FLUID_D3Q27: 27, FLAME_FLUID_D3Q19: 19}
+MAGNETIC_COUNT = {FLAME_MAGNETIC_D3Q7: 7, FLAME_MAGNETIC_D3Q15: 15, FLAME_MAGNETIC_D3Q27: 27}
 
 
 class flame_params(ctypes.Structure):
@@ -38,6 +43,7 @@ class flame_params(ctypes.Structure):
         ("init_noneq", ctypes.c_int32),
         ("force_u", ctypes.c_void_p), ("force_b", ctypes.c_void_p),
         ("collision", ctypes.c_int32), ("magnetic", ctypes.c_int32),
+        ("fluid_lattice", ctypes.c_int32), ("magnetic_lattice", ctypes.c_int32),
     ]
 
 
@@ -111,9 +117,11 @@ def flame_storage_bytes(params: flame_params) -> int:
 
 
 def flame_rest_populations(params: flame_params):
-    """(f_rest[27], g_rest[21]) as lists of floats."""
-    f = (ctypes.c_double * 27)()
-    g = (ctypes.c_double * 21)()
+    """(f_rest[q], g_rest[3 m]) as lists of floats (q = 27, m = 7 on the paper's velocity sets)."""
+    q = FLUID_COUNT[params.fluid_lattice]
+    m = MAGNETIC_COUNT[params.magnetic_lattice]
+    f = (ctypes.c_double * q)()
+    g = (ctypes.c_double * (3 * m))()
     _check(load().flame_rest_populations(ctypes.byref(params), f, g))
     return list(f), list(g)
 

@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libflame.so")
-SOURCES = ["flame_step.hip", "flame_api.hip", "flame_adjoint.hip"]
+SOURCES = ["flame_step.hip", "flame_api.hip", "flame_adjoint.hip", "flame_lattice.hip"]
 ARCH = os.environ.get("FLAME_OFFLOAD_ARCH", "gfx950")
 
 

@@ -29,13 +29,32 @@ struct AdjArgs {
 };
 
 constexpr int kAdjThreads = 256;
+// Minimum waves per SIMD the reverse-pass kernels are compiled for (0: the compiler's choice).
+#ifndef FLAME_ADJ_WAVES_PER_EU
+#define FLAME_ADJ_WAVES_PER_EU 0
+#endif
+#if FLAME_ADJ_WAVES_PER_EU > 0
+#define FLAME_ADJ_BOUNDS __launch_bounds__(kAdjThreads, FLAME_ADJ_WAVES_PER_EU)
+#else
+#define FLAME_ADJ_BOUNDS __launch_bounds__(kAdjThreads)
+#endif
+
+// Keeps the scheduler from moving the gathers of the next step's adjoints above the forward
+// recomputation, so the pre-collision populations are dead before those values arrive (fewer
+// registers live at once). Off unless FLAME_ADJ_FENCE is set.
+#ifndef FLAME_ADJ_FENCE
+#define FLAME_ADJ_FENCE 0
+#endif
+__device__ __forceinline__ void adj_phase_fence() {
+  if (FLAME_ADJ_FENCE) __builtin_amdgcn_sched_barrier(0);
+}
 
 __device__ __forceinline__ size_t anode(int x, int y, int z, int nx, int ny) {
   return (static_cast<size_t>(z) * ny + y) * nx + x;
 }
 
 template <typename R, bool MOMENT>
-__global__ __launch_bounds__(kAdjThreads) void adjoint_step_kernel(AdjArgs<R> a) {
+__global__ FLAME_ADJ_BOUNDS void adjoint_step_kernel(AdjArgs<R> a) {
   unsigned bx, by, bz;
   logical_block((a.nx + blockDim.x - 1) / blockDim.x, a.ny, a.nz, bx, by, bz);
   const int x = bx * blockDim.x + threadIdx.x, y = by, z = bz;
@@ -43,17 +62,24 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_step_kernel(AdjArgs<R> a)
   const int nx = a.nx, ny = a.ny, nz = a.nz;
   const size_t n = a.n;
   const size_t cell = anode(x, y, z, nx, ny);
-  R f[kQ], g[kM], J[3], mf[kQ], mg[kM], F[3], S[3];
+  R F[3];
+  VjpState<R> st;
+  {
+    R f[kQ], g[kM], J[3], S[3];
 #pragma unroll
-  for (int q = 0; q < kQ; ++q) f[q] = a.state[static_cast<size_t>(q) * n + cell];
+    for (int q = 0; q < kQ; ++q) f[q] = a.state[static_cast<size_t>(q) * n + cell];
 #pragma unroll
-  for (int q = 0; q < kM; ++q) g[q] = a.state[static_cast<size_t>(kQ + q) * n + cell];
+    for (int q = 0; q < kM; ++q) g[q] = a.state[static_cast<size_t>(kQ + q) * n + cell];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    J[c] = a.state[static_cast<size_t>(kQ + kM + c) * n + cell];
-    F[c] = a.force_u ? a.force_u[static_cast<size_t>(c) * n + cell] : R(0);
-    S[c] = a.force_b ? a.force_b[static_cast<size_t>(c) * n + cell] : R(0);
+    for (int c = 0; c < 3; ++c) {
+      J[c] = a.state[static_cast<size_t>(kQ + kM + c) * n + cell];
+      F[c] = a.force_u ? a.force_u[static_cast<size_t>(c) * n + cell] : R(0);
+      S[c] = a.force_b ? a.force_b[static_cast<size_t>(c) * n + cell] : R(0);
+    }
+    st = vjp_forward<R, MOMENT>(f, g, F, S, J, a.k);
   }
+  adj_phase_fence();
+  R mf[kQ], mg[kM];
 #pragma unroll
   for (int i = 0; i < kQ; ++i)
     mf[i] = a.lam_next[static_cast<size_t>(i) * n +
@@ -65,7 +91,7 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_step_kernel(AdjArgs<R> a)
     for (int c = 0; c < 3; ++c) mg[i * 3 + c] = a.lam_next[static_cast<size_t>(kQ + i * 3 + c) * n + dn];
   }
   R lf[kQ], lg[kM], lJ[3];
-  collide_vjp<R, MOMENT>(f, g, F, S, J, a.k, mf, mg, lf, lg, lJ);
+  vjp_reverse<R, MOMENT>(st, F, a.k, mf, mg, lf, lg, lJ);
 #pragma unroll
   for (int q = 0; q < kQ; ++q) a.lam[static_cast<size_t>(q) * n + cell] = lf[q];
 #pragma unroll
@@ -91,7 +117,7 @@ struct AdjTraceArgs {
 };
 
 template <typename S>
-__global__ __launch_bounds__(kAdjThreads) void adjoint_trace_kernel(AdjTraceArgs<S> a) {
+__global__ FLAME_ADJ_BOUNDS void adjoint_trace_kernel(AdjTraceArgs<S> a) {
   using E = Enc<S>;
   using R = typename E::R;
   unsigned bx, by, bz;
@@ -101,38 +127,33 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_trace_kernel(AdjTraceArgs
   const int nx = a.nx, ny = a.ny, nz = a.nz;
   const size_t n = a.n;
   const size_t cell = anode(x, y, z, nx, ny);
-  R f[kQ], g[kM], F[3], Sb[3];
-#pragma unroll
-  for (int i = 0; i < kQ; ++i)
-    f[i] = E::dec(a.src[static_cast<size_t>(i) * n +
-                        anode(wrap(x - cq(i, 0), nx), wrap(y - cq(i, 1), ny), wrap(z - cq(i, 2), nz), nx, ny)],
-                  R(1.0 / E::fscale(i)));
-#pragma unroll
-  for (int i = 0; i < 7; ++i) {
-    const size_t sn = anode(wrap(x - xim(i, 0), nx), wrap(y - xim(i, 1), ny), wrap(z - xim(i, 2), nz), nx, ny);
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-      g[i * 3 + c] = E::dec(a.src[static_cast<size_t>(kQ + i * 3 + c) * n + sn], R(1.0 / E::mscale(i)));
-  }
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    F[c] = a.force_u ? a.force_u[static_cast<size_t>(c) * n + cell] : R(0);
-    Sb[c] = a.force_b ? a.force_b[static_cast<size_t>(c) * n + cell] : R(0);
-  }
-  // the forward step's J, in its order of operations
-  R J[3];
+  R F[3];
+  VjpState<R> st;
   {
-    const FluidMoments<R> m = fluid_moments(f);
-    const R inv_rho = R(1) / (R(1) + m.drho);
-    const R U[3] = {(m.jx + R(0.5) * F[0]) * inv_rho, (m.jy + R(0.5) * F[1]) * inv_rho,
-                    (m.jz + R(0.5) * F[2]) * inv_rho};
-    R b[3], lam[3][3];
-    magnetic_moments(g, b, lam);
+    // the step's pre-collision state pulled from the lattice, and the forward step's J recomputed
+    // from it (moment route, same order of operations)
+    R f[kQ], g[kM], Sb[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) b[c] = b_component(g, c, R(0.5) * Sb[c]);
-    const R B[3] = {a.k.b0[0] + b[0], a.k.b0[1] + b[1], a.k.b0[2] + b[2]};
-    current_from_moments(lam, U, B, a.k.alpha, a.k.omega_b, J);
+    for (int i = 0; i < kQ; ++i)
+      f[i] = E::dec(a.src[static_cast<size_t>(i) * n +
+                          anode(wrap(x - cq(i, 0), nx), wrap(y - cq(i, 1), ny), wrap(z - cq(i, 2), nz), nx, ny)],
+                    R(1.0 / E::fscale(i)));
+#pragma unroll
+    for (int i = 0; i < 7; ++i) {
+      const size_t sn = anode(wrap(x - xim(i, 0), nx), wrap(y - xim(i, 1), ny), wrap(z - xim(i, 2), nz), nx, ny);
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        g[i * 3 + c] = E::dec(a.src[static_cast<size_t>(kQ + i * 3 + c) * n + sn], R(1.0 / E::mscale(i)));
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      F[c] = a.force_u ? a.force_u[static_cast<size_t>(c) * n + cell] : R(0);
+      Sb[c] = a.force_b ? a.force_b[static_cast<size_t>(c) * n + cell] : R(0);
+    }
+    const R unused[3] = {R(0), R(0), R(0)};
+    st = vjp_forward<R, true>(f, g, F, Sb, unused, a.k);
   }
+  adj_phase_fence();
   R mf[kQ], mg[kM];
 #pragma unroll
   for (int i = 0; i < kQ; ++i)
@@ -145,7 +166,7 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_trace_kernel(AdjTraceArgs
     for (int c = 0; c < 3; ++c) mg[i * 3 + c] = a.lam_next[static_cast<size_t>(kQ + i * 3 + c) * n + dn];
   }
   R lf[kQ], lg[kM], lJ[3];
-  collide_vjp<R, true>(f, g, F, Sb, J, a.k, mf, mg, lf, lg, lJ);
+  vjp_reverse<R, true>(st, F, a.k, mf, mg, lf, lg, lJ);
 #pragma unroll
   for (int q = 0; q < kQ; ++q) a.lam[static_cast<size_t>(q) * n + cell] = lf[q];
 #pragma unroll
@@ -315,8 +336,9 @@ extern "C" {
 
 flame_status flame_step_save(flame_ctx* c, void* state) {
   if (!c) return FLAME_E_INVAL;
-  if (step_model(c->p) != 0) {
-    c->err = "reverse mode is built for the paper's model only (central-moment fluid, Hall equilibrium)";
+  if (!reverse_mode_built(c->p)) {
+    c->err = "reverse mode is built for the paper's model only (central-moment fluid, Hall equilibrium, "
+             "D3Q27 / D3Q7 velocity sets)";
     return FLAME_E_UNSUPPORTED;
   }
   if (!state) {
@@ -339,8 +361,9 @@ flame_status flame_step_save(flame_ctx* c, void* state) {
 
 flame_status flame_trace_step(flame_ctx* c, const void* src, void* dst) {
   if (!c) return FLAME_E_INVAL;
-  if (step_model(c->p) != 0) {
-    c->err = "reverse mode is built for the paper's model only (central-moment fluid, Hall equilibrium)";
+  if (!reverse_mode_built(c->p)) {
+    c->err = "reverse mode is built for the paper's model only (central-moment fluid, Hall equilibrium, "
+             "D3Q27 / D3Q7 velocity sets)";
     return FLAME_E_UNSUPPORTED;
   }
   if (c->p.jmode != FLAME_J_MOMENT || c->p.layout != FLAME_LAYOUT_AA) {
@@ -369,8 +392,9 @@ flame_status flame_trace_step(flame_ctx* c, const void* src, void* dst) {
 
 flame_status flame_adjoint_step(flame_ctx* c, const void* state, const void* lam_next, void* lam, void* lam_j) {
   if (!c) return FLAME_E_INVAL;
-  if (step_model(c->p) != 0) {
-    c->err = "reverse mode is built for the paper's model only (central-moment fluid, Hall equilibrium)";
+  if (!reverse_mode_built(c->p)) {
+    c->err = "reverse mode is built for the paper's model only (central-moment fluid, Hall equilibrium, "
+             "D3Q27 / D3Q7 velocity sets)";
     return FLAME_E_UNSUPPORTED;
   }
   if (!state || !lam_next || !lam || lam == lam_next || (c->p.jmode == FLAME_J_STENCIL && !lam_j)) {
@@ -388,8 +412,9 @@ flame_status flame_adjoint_step(flame_ctx* c, const void* state, const void* lam
 
 flame_status flame_adjoint_trace_step(flame_ctx* c, const void* src, const void* lam_next, void* lam) {
   if (!c) return FLAME_E_INVAL;
-  if (step_model(c->p) != 0) {
-    c->err = "reverse mode is built for the paper's model only (central-moment fluid, Hall equilibrium)";
+  if (!reverse_mode_built(c->p)) {
+    c->err = "reverse mode is built for the paper's model only (central-moment fluid, Hall equilibrium, "
+             "D3Q27 / D3Q7 velocity sets)";
     return FLAME_E_UNSUPPORTED;
   }
   if (c->p.jmode != FLAME_J_MOMENT || c->p.layout != FLAME_LAYOUT_AA) {
@@ -417,8 +442,9 @@ flame_status flame_adjoint_init(flame_ctx* c, const void* lam0, const double* u,
                                 const double* grad_u, const double* grad_b, double* g_u, double* g_b,
                                 double* g_grad_u, double* g_grad_b) {
   if (!c) return FLAME_E_INVAL;
-  if (step_model(c->p) != 0) {
-    c->err = "reverse mode is built for the paper's model only (central-moment fluid, Hall equilibrium)";
+  if (!reverse_mode_built(c->p)) {
+    c->err = "reverse mode is built for the paper's model only (central-moment fluid, Hall equilibrium, "
+             "D3Q27 / D3Q7 velocity sets)";
     return FLAME_E_UNSUPPORTED;
   }
   if (!lam0 || !u || !b || !g_u || !g_b) {

@@ -2,6 +2,7 @@
 // state, canonical access, node fields, FP64 reductions and shell spectra.
 
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -698,12 +699,26 @@ std::string validate(const flame_params* p) {
   if (p->layout != FLAME_LAYOUT_AB && p->layout != FLAME_LAYOUT_AA) return "unknown layout";
   if (p->collision != FLAME_COLLISION_CENTRAL && p->collision != FLAME_COLLISION_BGK) return "unknown collision";
   if (p->magnetic != FLAME_MAGNETIC_HALL && p->magnetic != FLAME_MAGNETIC_EMHD) return "unknown magnetic model";
+  if (p->fluid_lattice != FLAME_FLUID_D3Q27 && p->fluid_lattice != FLAME_FLUID_D3Q19) return "unknown fluid lattice";
+  if (p->magnetic_lattice != FLAME_MAGNETIC_D3Q7 && p->magnetic_lattice != FLAME_MAGNETIC_D3Q15 &&
+      p->magnetic_lattice != FLAME_MAGNETIC_D3Q27)
+    return "unknown magnetic lattice";
+  return "";
+}
+
+// Valid parameters whose combination is not built ("" if it is).
+std::string unsupported(const flame_params* p) {
+  if (lattice_variant(*p) && p->jmode != FLAME_J_MOMENT)
+    return "the lattice variants run the moment route of J only";
+  if (p->fluid_lattice == FLAME_FLUID_D3Q19 && p->collision != FLAME_COLLISION_BGK)
+    return "the central-moment collision is built on the D3Q27 fluid set; D3Q19 runs the BGK collision";
   return "";
 }
 
 size_t values_per_node(const flame_params& p) {
-  if (p.layout == FLAME_LAYOUT_AB) return 96;
-  return p.jmode == FLAME_J_STENCIL ? 69 : 48;
+  const size_t one = static_cast<size_t>(fluid_count(p)) + 3 * static_cast<size_t>(mag_count(p));
+  if (p.layout == FLAME_LAYOUT_AB) return 2 * one;
+  return p.jmode == FLAME_J_STENCIL ? one + 3 * static_cast<size_t>(mag_count(p)) : one;
 }
 
 template <typename S>
@@ -791,7 +806,7 @@ constexpr double kSoundSpeed = 0.57735026918962576;
 // The reductions of the current state: block partials into partials (c->red_blocks x FLAME_NRED
 // doubles), merged in a fixed order into out (FLAME_NRED doubles, device). Asynchronous.
 hipError_t launch_reduce(const flame_ctx* c, double* partials, double* out) {
-  hipError_t e = by_storage(c, [&](auto tag) {
+  hipError_t e = lattice_variant(c->p) ? variant_launch_reduce(c, partials) : by_storage(c, [&](auto tag) {
     using S = decltype(tag);
     hipLaunchKernelGGL(reduce_kernel<S>, dim3(c->red_blocks), dim3(kRedThreads), 0, c->stream, make_aux<S>(c),
                        partials);
@@ -809,13 +824,14 @@ namespace flame {
 SetPtrs set_ptrs(const flame_ctx* c) {
   const size_t vb = value_bytes(c->p.storage);
   const size_t n = c->stride;
+  const size_t nf = fluid_count(c->p), ng = 3 * static_cast<size_t>(mag_count(c->p));
   char* base = static_cast<char*>(c->storage);
   SetPtrs s{};
   if (c->p.layout == FLAME_LAYOUT_AB) {
     char* F0 = base;
-    char* F1 = base + 27 * n * vb;
-    char* G0 = base + 54 * n * vb;
-    char* G1 = G0 + 21 * n * vb;
+    char* F1 = base + nf * n * vb;
+    char* G0 = base + 2 * nf * n * vb;
+    char* G1 = G0 + ng * n * vb;
     s.f_src = c->cur ? F1 : F0;
     s.f_dst = c->cur ? F0 : F1;
     s.g_src = c->cur ? G1 : G0;
@@ -825,9 +841,9 @@ SetPtrs set_ptrs(const flame_ctx* c) {
   } else {
     s.f_src = s.f_dst = base;
     s.fluid_aa = true;
-    char* G0 = base + 27 * n * vb;
+    char* G0 = base + nf * n * vb;
     if (c->p.jmode == FLAME_J_STENCIL) {
-      char* G1 = G0 + 21 * n * vb;
+      char* G1 = G0 + ng * n * vb;
       s.g_src = c->cur ? G1 : G0;
       s.g_dst = c->cur ? G0 : G1;
       s.mag_aa = false;
@@ -844,6 +860,11 @@ extern "C" {
 
 flame_status flame_rest_populations(const flame_params* p, double* f_rest, double* g_rest) {
   if (!p) return FLAME_E_INVAL;
+  if (lattice_variant(*p)) {
+    if (!validate(p).empty()) return FLAME_E_INVAL;
+    variant_rest(*p, f_rest, g_rest);
+    return FLAME_OK;
+  }
   // f^mhd(0)(1, 0, b0) = w_i + (w_i / 2 c_s^4) M(b0) : (c c - c_s^2 I), M = |b0|^2/2 I - b0 b0,
   // with M : (c c - I/3) = |b0|^2/2 (|c|^2 - 1/3) - (b0 . c)^2
   const double* B0 = p->b0;
@@ -860,7 +881,7 @@ flame_status flame_rest_populations(const flame_params* p, double* f_rest, doubl
 }
 
 size_t flame_storage_bytes(const flame_params* p) {
-  if (!validate(p).empty()) return 0;
+  if (!validate(p).empty() || !unsupported(p).empty()) return 0;
   return values_per_node(*p) * value_bytes(p->storage) * population_stride(*p);
 }
 
@@ -872,6 +893,8 @@ flame_status flame_init(const flame_params* p, const double* u, const double* b,
   *out = nullptr;
   const std::string bad = validate(p);
   if (!bad.empty()) return fail(nullptr, FLAME_E_INVAL, bad);
+  const std::string not_built = unsupported(p);
+  if (!not_built.empty()) return fail(nullptr, FLAME_E_UNSUPPORTED, not_built);
   if (!u || !b) return fail(nullptr, FLAME_E_INVAL, "u and b must be given");
   if (!storage) return fail(nullptr, FLAME_E_INVAL, "storage is NULL");
   if (reinterpret_cast<uintptr_t>(storage) % 256 != 0) return fail(nullptr, FLAME_E_INVAL, "storage must be 256-byte aligned");
@@ -887,8 +910,11 @@ flame_status flame_init(const flame_params* p, const double* u, const double* b,
   c->storage = storage;
   c->omega = 1.0 / (3.0 * p->nu + 0.5);
   c->omega_b = 1.0 / (4.0 * p->eta + 0.5);
+  // launch-shape tuning (multiples of 64 threads per row block; any positive plane count)
+  if (const char* v = getenv("FLAME_ZCHUNK_PLANES")) c->zchunk = std::max(0, atoi(v));
+  if (const char* v = getenv("FLAME_ROW_THREADS")) c->row_tx = std::max(0, atoi(v)) / 64 * 64;
   const double* B0 = p->b0;
-  flame_rest_populations(p, c->frest, nullptr);
+  flame_rest_populations(p, c->frest, nullptr);   // q <= 27 values
   auto bail = [&](flame_status code) {
     g_init_error = c->err;
     delete c;
@@ -906,7 +932,7 @@ flame_status flame_init(const flame_params* p, const double* u, const double* b,
   }
   // initial state into the canonical slots of copy 0
   const SetPtrs s = set_ptrs(c);
-  hipError_t e = by_storage(c, [&](auto tag) {
+  hipError_t e = lattice_variant(*p) ? variant_launch_init(c, u, b, grad_u, grad_b) : by_storage(c, [&](auto tag) {
     using S = decltype(tag);
     using R = typename Enc<S>::R;
     InitArgs<S> a;
@@ -974,7 +1000,7 @@ flame_status flame_step(flame_ctx* c, int64_t nsteps) {
 
 flame_status flame_moments(flame_ctx* c, double* rho, double* u, double* b, double* j, double* divb) {
   if (!c) return FLAME_E_INVAL;
-  hipError_t e = by_storage(c, [&](auto tag) {
+  hipError_t e = lattice_variant(c->p) ? variant_launch_moments(c, rho, u, b, j, divb) : by_storage(c, [&](auto tag) {
     using S = decltype(tag);
     hipLaunchKernelGGL(moments_kernel<S>, dim3(blocks_for(c->n, 256)), dim3(256), 0, c->stream,
                        make_aux<S>(c), rho, u, b, j, divb);
@@ -1048,7 +1074,8 @@ flame_status shell_spectrum(flame_ctx* c, int32_t field, int32_t nshells, int k2
   for (int s = 0; s < nshells; ++s) e_k[s] = 0.0;
   const double norm2 = 1.0 / (static_cast<double>(c->n) * static_cast<double>(c->n));
   for (int comp = 0; comp < 3; ++comp) {
-    hipError_t e = by_storage(c, [&](auto tag) {
+    hipError_t e = lattice_variant(c->p) ? variant_launch_component(c, field, comp, c->spec_real)
+                                         : by_storage(c, [&](auto tag) {
       using S = decltype(tag);
       hipLaunchKernelGGL(field_component_kernel<S>, dim3(blocks_for(c->n, 256)), dim3(256), 0, c->stream,
                          make_aux<S>(c), field, comp, c->spec_real);
@@ -1148,7 +1175,7 @@ flame_status energy_transfer(flame_ctx* c, int32_t nshells, double* t_adv, doubl
   hipfftDoubleComplex* Bh = w.cplx + 3 * nh;
   hipfftDoubleComplex* spec = w.cplx + 6 * nh;
   const unsigned gn = blocks_for(n, 256), gh = blocks_for(nh, 256);
-  hipError_t e = by_storage(c, [&](auto tag) {
+  hipError_t e = lattice_variant(c->p) ? variant_launch_moments(c, nullptr, U, B, J, nullptr) : by_storage(c, [&](auto tag) {
     using S = decltype(tag);
     hipLaunchKernelGGL(moments_kernel<S>, dim3(gn), dim3(256), 0, c->stream, make_aux<S>(c), nullptr, U, B, J,
                        nullptr);
@@ -1228,7 +1255,7 @@ flame_status flame_energy_transfer(flame_ctx* c, int32_t nshells, double* t_adv,
 
 flame_status flame_get_populations(flame_ctx* c, double* dst, int32_t deviations) {
   if (!c || !dst) return c ? fail(c, FLAME_E_INVAL, "dst is NULL") : FLAME_E_INVAL;
-  hipError_t e = by_storage(c, [&](auto tag) {
+  hipError_t e = lattice_variant(c->p) ? variant_launch_get(c, deviations, dst) : by_storage(c, [&](auto tag) {
     using S = decltype(tag);
     hipLaunchKernelGGL(get_kernel<S>, dim3(blocks_for(c->n, 256)), dim3(256), 0, c->stream, make_view<S>(c),
                        make_rest(c, deviations), dst);
@@ -1244,7 +1271,7 @@ flame_status flame_set_populations(flame_ctx* c, const double* src, int32_t devi
   c->parity = 0;
   c->steps = 0;
   const SetPtrs s = set_ptrs(c);
-  hipError_t e = by_storage(c, [&](auto tag) {
+  hipError_t e = lattice_variant(c->p) ? variant_launch_set(c, deviations, src) : by_storage(c, [&](auto tag) {
     using S = decltype(tag);
     hipLaunchKernelGGL(set_kernel<S>, dim3(blocks_for(c->n, 256)), dim3(256), 0, c->stream,
                        static_cast<S*>(s.f_src), static_cast<S*>(s.g_src), c->n, c->stride, make_placement(c),
@@ -1259,7 +1286,7 @@ flame_status flame_gather(flame_ctx* c, const int64_t* cells, int64_t n, double*
   if (!c) return FLAME_E_INVAL;
   if (n < 0 || (n > 0 && (!cells || !out))) return fail(c, FLAME_E_INVAL, "bad gather arguments");
   if (n == 0) return FLAME_OK;
-  hipError_t e = by_storage(c, [&](auto tag) {
+  hipError_t e = lattice_variant(c->p) ? variant_launch_gather(c, deviations, cells, n, out) : by_storage(c, [&](auto tag) {
     using S = decltype(tag);
     hipLaunchKernelGGL(gather_kernel<S>, dim3(blocks_for(static_cast<size_t>(n), 256)), dim3(256), 0, c->stream,
                        make_view<S>(c), make_rest(c, deviations), cells, n, out);
@@ -1269,15 +1296,17 @@ flame_status flame_gather(flame_ctx* c, const int64_t* cells, int64_t n, double*
   return FLAME_OK;
 }
 
-size_t flame_trace_bytes(const flame_ctx* c) { return c ? 48 * c->n * value_bytes(c->p.storage) : 0; }
+size_t flame_trace_bytes(const flame_ctx* c) {
+  return c && reverse_mode_built(c->p) ? 48 * c->n * value_bytes(c->p.storage) : 0;
+}
 
 flame_status flame_trace_export(flame_ctx* c, void* lat) {
   if (!c) return FLAME_E_INVAL;
-  if (!lat) return fail(c, FLAME_E_INVAL, "lat is NULL");
   if (c->p.layout != FLAME_LAYOUT_AA || c->p.jmode != FLAME_J_MOMENT)
     return fail(c, FLAME_E_UNSUPPORTED, "trace export is available on the moment route with the AA layout only");
-  if (step_model(c->p) != 0)
-    return fail(c, FLAME_E_UNSUPPORTED, "reverse mode is built for the paper's model only");
+  if (!reverse_mode_built(c->p))
+    return fail(c, FLAME_E_UNSUPPORTED, "reverse mode is built for the paper's model and velocity sets only");
+  if (!lat) return fail(c, FLAME_E_INVAL, "lat is NULL");
   hipError_t e = by_storage(c, [&](auto tag) {
     using S = decltype(tag);
     hipLaunchKernelGGL(export_kernel<S>, dim3(blocks_for(c->n, 256)), dim3(256), 0, c->stream, make_view<S>(c),
@@ -1290,6 +1319,8 @@ flame_status flame_trace_export(flame_ctx* c, void* lat) {
 
 flame_status flame_adjoint_fields(flame_ctx* c, const double* dl_du, const double* dl_db, void* lam) {
   if (!c) return FLAME_E_INVAL;
+  if (!reverse_mode_built(c->p))
+    return fail(c, FLAME_E_UNSUPPORTED, "reverse mode is built for the paper's model and velocity sets only");
   if (!lam) return fail(c, FLAME_E_INVAL, "lam is NULL");
   hipError_t e = by_storage(c, [&](auto tag) {
     using S = decltype(tag);

@@ -356,27 +356,52 @@ struct AxisD {
 // lf, lg = d loss / d(pre-collision deviations) through this node's collision, and lJ =
 // d loss / dJ (stencil route: J is an input computed from neighbouring fields, Jst; on the moment
 // route lJ is folded into lf, lg and returned as zero). F, S: forcing at the node.
-template <typename R, bool MOMENT>
-FLAME_HD void collide_vjp(const R (&f)[kQ], const R (&g)[kM], const R (&F)[3], const R (&S)[3],
-                          const R (&Jst)[3], const PhysConst<R>& k, const R (&mf)[kQ], const R (&mg)[kM],
-                          R (&lf)[kQ], R (&lg)[kM], R (&lJ)[3]) {
-  // ---- forward recomputation
-  const FluidMoments<R> m = fluid_moments(f);
-  const R rho = R(1) + m.drho;
-  const R inv_rho = R(1) / rho;
-  const R U[3] = {(m.jx + R(0.5) * F[0]) * inv_rho, (m.jy + R(0.5) * F[1]) * inv_rho,
-                  (m.jz + R(0.5) * F[2]) * inv_rho};
-  R b[3], lam[3][3];
-  magnetic_moments(g, b, lam);
-#pragma unroll
-  for (int c = 0; c < 3; ++c) b[c] += R(0.5) * S[c];
-  const R b0[3] = {k.b0[0], k.b0[1], k.b0[2]};
-  const R B[3] = {b0[0] + b[0], b0[1] + b[1], b0[2] + b[2]};
-  R J[3];
-  if (MOMENT) current_from_moments(lam, U, B, k.alpha, k.omega_b, J);
-  else { J[0] = Jst[0]; J[1] = Jst[1]; J[2] = Jst[2]; }
-  const R V[3] = {U[0] - k.alpha * J[0], U[1] - k.alpha * J[1], U[2] - k.alpha * J[2]};
+// Forward quantities of one node that the reverse pass needs (recomputed from the pre-collision
+// state; J from the moments on the moment route, else the J the forward step used).
+template <typename R>
+struct VjpState {
+  FluidMoments<R> m;
+  R rho, inv_rho, U[3], b[3], B[3], J[3], V[3], lam[3][3];
+};
 
+template <typename R, bool MOMENT>
+FLAME_HD VjpState<R> vjp_forward(const R (&f)[kQ], const R (&g)[kM], const R (&F)[3], const R (&S)[3],
+                                 const R (&Jst)[3], const PhysConst<R>& k) {
+  VjpState<R> st;
+  st.m = fluid_moments(f);
+  st.rho = R(1) + st.m.drho;
+  st.inv_rho = R(1) / st.rho;
+  st.U[0] = (st.m.jx + R(0.5) * F[0]) * st.inv_rho;
+  st.U[1] = (st.m.jy + R(0.5) * F[1]) * st.inv_rho;
+  st.U[2] = (st.m.jz + R(0.5) * F[2]) * st.inv_rho;
+  magnetic_moments(g, st.b, st.lam);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    st.b[c] += R(0.5) * S[c];
+    st.B[c] = k.b0[c] + st.b[c];
+  }
+  if (MOMENT) current_from_moments(st.lam, st.U, st.B, k.alpha, k.omega_b, st.J);
+  else { st.J[0] = Jst[0]; st.J[1] = Jst[1]; st.J[2] = Jst[2]; }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) st.V[c] = st.U[c] - k.alpha * st.J[c];
+  return st;
+}
+
+// The reverse pass proper: lf, lg, lJ from the adjoints mf, mg of the post-collision populations
+// at the forward quantities st. It reads neither the pre-collision populations nor S, so a kernel
+// can drop those before it gathers mf and mg.
+template <typename R, bool MOMENT>
+FLAME_HD void vjp_reverse(const VjpState<R>& st, const R (&F)[3], const PhysConst<R>& k, const R (&mf)[kQ],
+                          const R (&mg)[kM], R (&lf)[kQ], R (&lg)[kM], R (&lJ)[3]) {
+  const FluidMoments<R>& m = st.m;
+  const R rho = st.rho, inv_rho = st.inv_rho;
+  const R(&U)[3] = st.U;
+  const R(&b)[3] = st.b;
+  const R(&B)[3] = st.B;
+  const R(&J)[3] = st.J;
+  const R(&V)[3] = st.V;
+  const R(&lam)[3][3] = st.lam;
+  const R b0[3] = {k.b0[0], k.b0[1], k.b0[2]};
   R lU[3] = {R(0), R(0), R(0)}, lb[3] = {R(0), R(0), R(0)}, lB[3] = {R(0), R(0), R(0)};
   R lrho = R(0);
   R llam[3][3] = {};
@@ -553,6 +578,13 @@ FLAME_HD void collide_vjp(const R (&f)[kQ], const R (&g)[kM], const R (&F)[3], c
       lg[(4 + a) * 3 + c] += llam[a][c];
       lg[(1 + a) * 3 + c] -= llam[a][c];
     }
+}
+
+template <typename R, bool MOMENT>
+FLAME_HD void collide_vjp(const R (&f)[kQ], const R (&g)[kM], const R (&F)[3], const R (&S)[3],
+                          const R (&Jst)[3], const PhysConst<R>& k, const R (&mf)[kQ], const R (&mg)[kM],
+                          R (&lf)[kQ], R (&lg)[kM], R (&lJ)[3]) {
+  vjp_reverse<R, MOMENT>(vjp_forward<R, MOMENT>(f, g, F, S, Jst, k), F, k, mf, mg, lf, lg, lJ);
 }
 
 // ------------------------------------------------------------------ initial state of a node

@@ -23,6 +23,11 @@ struct flame_ctx {
   double frest[27]{};        // f^mhd(0)(1, 0, b0)
   double omega = 0, omega_b = 0;
   double cfl = 0;
+  // launch shape (tuning; read from the environment at flame_init, results do not depend on it):
+  // planes per workgroup of the stencil kernel (0: the built-in 32) and threads per row block of
+  // the node-local kernels (0: the row rounded up to whole wavefronts, at most 256)
+  int zchunk = 0;
+  int row_tx = 0;
   std::string err;
   // library-owned scratch
   double* red_partials = nullptr;
@@ -70,6 +75,17 @@ inline int step_model(const flame_params& p) {
 inline bool mag_two_lattice(const flame_params& p) {
   return p.layout == FLAME_LAYOUT_AB || p.jmode == FLAME_J_STENCIL;
 }
+// Velocity sets: a run on anything but the paper's D3Q27 fluid and D3Q7 magnetic sets goes
+// through the lattice-variant kernels (flame_lattice.hip).
+inline bool lattice_variant(const flame_params& p) {
+  return p.fluid_lattice != FLAME_FLUID_D3Q27 || p.magnetic_lattice != FLAME_MAGNETIC_D3Q7;
+}
+inline int fluid_count(const flame_params& p) { return p.fluid_lattice == FLAME_FLUID_D3Q19 ? 19 : 27; }
+inline int mag_count(const flame_params& p) {
+  return p.magnetic_lattice == FLAME_MAGNETIC_D3Q15 ? 15 : p.magnetic_lattice == FLAME_MAGNETIC_D3Q27 ? 27 : 7;
+}
+// Reverse mode and trace lattices are built for the paper's model and velocity sets only.
+inline bool reverse_mode_built(const flame_params& p) { return step_model(p) == 0 && !lattice_variant(p); }
 SetPtrs set_ptrs(const flame_ctx* c);
 
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2): hardware
@@ -100,10 +116,26 @@ __device__ __forceinline__ void logical_block(unsigned gx, unsigned gy, unsigned
 // wavefronts, at most 256 (longer rows take several blocks), so that short rows leave no wave
 // of a block idle.
 inline unsigned row_threads(int nx) { return static_cast<unsigned>(std::min(256, (nx + 63) / 64 * 64)); }
+inline unsigned row_threads(const flame_ctx* c) {
+  return c->row_tx > 0 ? static_cast<unsigned>(std::min(c->row_tx, (c->p.nx + 63) / 64 * 64)) : row_threads(c->p.nx);
+}
 
 // One fused step over the sets s, whose population arrays are stride elements apart; with
 // save != null also writes the pre-collision state of every node (arithmetic type,
 // [48 populations + 3 J][n]).
 hipError_t launch_step(const flame_ctx* c, const SetPtrs& s, size_t stride, void* save);
+
+// Lattice-variant kernels (flame_lattice.hip), each enqueued on the context's stream.
+hipError_t variant_launch_step(const flame_ctx* c, const SetPtrs& s);
+hipError_t variant_launch_init(const flame_ctx* c, const double* u, const double* b, const double* grad_u,
+                               const double* grad_b);
+hipError_t variant_launch_get(const flame_ctx* c, int deviations, double* dst);
+hipError_t variant_launch_gather(const flame_ctx* c, int deviations, const int64_t* cells, int64_t cnt, double* out);
+hipError_t variant_launch_set(const flame_ctx* c, int deviations, const double* src);
+hipError_t variant_launch_moments(const flame_ctx* c, double* rho, double* u, double* b, double* j, double* divb);
+hipError_t variant_launch_component(const flame_ctx* c, int field, int comp, double* out);
+hipError_t variant_launch_reduce(const flame_ctx* c, double* partials);
+// Rest populations of the lattice variants (host): f_rest[q], g_rest[3 m].
+void variant_rest(const flame_params& p, double* f_rest, double* g_rest);
 
 }  // namespace flame

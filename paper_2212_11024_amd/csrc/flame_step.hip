@@ -17,8 +17,8 @@
 //   step_zmarch - stencil J: a workgroup owns a 64 x 4 tile of (x, y) and marches along z. It
 //     keeps the field fluctuation b of three consecutive planes in LDS (computed once per node
 //     from that node's own magnetic populations, which it holds in registers for the next
-//     iteration) plus, for the current plane, the one-node ring around the tile; J is the
-//     central-difference curl read from LDS.
+//     iteration) plus, for each plane, the one-node ring around the tile (computed one plane
+//     ahead); J is the central-difference curl read from LDS.
 
 #include <algorithm>
 
@@ -63,21 +63,11 @@ template <typename S>
 __device__ __forceinline__ S ld(const S* base, uint32_t off) {
   return *reinterpret_cast<const S*>(reinterpret_cast<const char*>(base) + off * static_cast<uint32_t>(sizeof(S)));
 }
-// Streaming load: the value is used once and shared with no other workgroup, so it should not
-// displace lines that neighbouring workgroups still read from L2.
-template <typename S>
-__device__ __forceinline__ S ld_stream(const S* base, uint32_t off) {
-  return __builtin_nontemporal_load(
-      reinterpret_cast<const S*>(reinterpret_cast<const char*>(base) + off * static_cast<uint32_t>(sizeof(S))));
-}
-#ifndef FLAME_ZMARCH_STREAM_FLUID
-#define FLAME_ZMARCH_STREAM_FLUID 0
-#endif
 // Stencil kernel: compute the ring of b around the tile one plane ahead, together with the
 // tile's own loads of that plane (the ring nodes' populations are the ones the neighbouring
-// tiles load at about the same time).
+// tiles load at about the same time); 0 computes it for the current plane.
 #ifndef FLAME_ZMARCH_RING_AHEAD
-#define FLAME_ZMARCH_RING_AHEAD 0
+#define FLAME_ZMARCH_RING_AHEAD 1
 #endif
 #ifndef FLAME_NT_STORES
 #define FLAME_NT_STORES 1
@@ -102,9 +92,8 @@ struct Planes {
   __device__ __forceinline__ uint32_t at(int dz) const { return p[dz + 1]; }
 };
 
-// Fluid populations of the node. FAA: in place (PAR selects the AA step); else pull. STREAM:
-// non-temporal loads.
-template <typename S, bool FAA, int PAR, bool STREAM = false>
+// Fluid populations of the node. FAA: in place (PAR selects the AA step); else pull.
+template <typename S, bool FAA, int PAR>
 __device__ __forceinline__ void load_fluid(const StepArgs<S>& a, const Rows& rw, const Planes& pl,
                                            typename Enc<S>::R (&f)[kQ]) {
   using E = Enc<S>;
@@ -114,7 +103,7 @@ __device__ __forceinline__ void load_fluid(const StepArgs<S>& a, const Rows& rw,
     const bool own = FAA && PAR == 0;
     const uint32_t off = own ? rw.at(0, 0) + pl.at(0) : rw.at(-cq(i, 0), -cq(i, 1)) + pl.at(-cq(i, 2));
     const S* base = a.f_src + static_cast<size_t>(FAA && PAR == 1 ? oppq(i) : i) * a.stride;
-    f[i] = E::dec(STREAM ? ld_stream(base, off) : ld(base, off), R(1.0 / E::fscale(i)));
+    f[i] = E::dec(ld(base, off), R(1.0 / E::fscale(i)));
   }
 }
 
@@ -316,7 +305,7 @@ __global__ __launch_bounds__(kTX * Tile<typename Enc<S>::R>::ty, FLAME_ZMARCH_WA
 #pragma unroll
     for (int c = 0; c < 3; ++c) sb[slot][ly + 1][lx + 1][c] = b_component(g, c, half_src(cell, c));
   };
-  // ring nodes of the current plane: two components of b from their seven pulled populations
+  // ring nodes of a plane: two components of b from their seven pulled populations
   auto ring = [&](int slot, const Planes& pl) {
     for (int task = tid; task < 2 * w + 2 * h; task += kTX * kTY) {
       int rx, ry, c0, c1;
@@ -378,7 +367,7 @@ __global__ __launch_bounds__(kTX * Tile<typename Enc<S>::R>::ty, FLAME_ZMARCH_WA
     if (active) {
       // the fluid half of the update needs no J: collide and store it before the barrier
       R f[kQ];
-      load_fluid<S, FAA, PAR, FLAME_ZMARCH_STREAM_FLUID != 0>(a, rw, pl, f);
+      load_fluid<S, FAA, PAR>(a, rw, pl, f);
       forcing_at(a, cell, F, Sb);
       if (SAVE) save_state(a.save, a.n, cell, f, g);
       const FluidMoments<R> m = fluid_moments(f);
@@ -422,8 +411,8 @@ static void launch_model(const flame_ctx* c, const SetPtrs& s, const StepArgs<S>
   const int par = c->parity;
   if (c->p.jmode == FLAME_J_STENCIL) {
     constexpr int kTY = Tile<R>::ty;
-    const dim3 block(kTX, kTY, 1);
     const dim3 grid(((c->p.nx + kTX - 1) / kTX) * ((c->p.ny + kTY - 1) / kTY) * ((c->p.nz + a.zchunk - 1) / a.zchunk));
+    const dim3 block(kTX, kTY, 1);
     if (!s.fluid_aa)
       hipLaunchKernelGGL((step_zmarch<S, false, 0, SAVE, MODEL>), grid, block, 0, c->stream, a);
     else if (par == 0)
@@ -431,7 +420,7 @@ static void launch_model(const flame_ctx* c, const SetPtrs& s, const StepArgs<S>
     else
       hipLaunchKernelGGL((step_zmarch<S, true, 1, SAVE, MODEL>), grid, block, 0, c->stream, a);
   } else {
-    const unsigned tx = row_threads(c->p.nx);
+    const unsigned tx = row_threads(c);
     const dim3 block(tx, 1, 1);
     const dim3 grid(((c->p.nx + tx - 1) / tx) * c->p.ny * c->p.nz);
     if (!s.fluid_aa)
@@ -463,7 +452,7 @@ static hipError_t launch_typed(const flame_ctx* c, const SetPtrs& s, size_t stri
   a.k.omega_b = R(c->omega_b);
   a.k.alpha = R(c->p.d_i);
   for (int i = 0; i < 3; ++i) a.k.b0[i] = R(c->p.b0[i]);
-  a.zchunk = c->p.jmode == FLAME_J_STENCIL ? std::min(c->p.nz, kZChunk) : 1;
+  a.zchunk = c->p.jmode == FLAME_J_STENCIL ? std::min(c->p.nz, c->zchunk > 0 ? c->zchunk : kZChunk) : 1;
   const int model = step_model(c->p);
   if constexpr (SAVE) {
     // the state-saving steps serve the adjoint, which is built for the paper's model only
@@ -481,6 +470,7 @@ static hipError_t launch_typed(const flame_ctx* c, const SetPtrs& s, size_t stri
 }
 
 hipError_t launch_step(const flame_ctx* c, const SetPtrs& s, size_t stride, void* save) {
+  if (lattice_variant(c->p)) return save ? hipErrorInvalidValue : variant_launch_step(c, s);
   switch (c->p.storage) {
     case FLAME_F64:
       return save ? launch_typed<double, true>(c, s, stride, save) : launch_typed<double, false>(c, s, stride, save);

@@ -15,6 +15,8 @@ JMODE = {"moment": L.FLAME_J_MOMENT, "stencil": L.FLAME_J_STENCIL}
 LAYOUT = {"ab": L.FLAME_LAYOUT_AB, "aa": L.FLAME_LAYOUT_AA}
 COLLISION = {"central": L.FLAME_COLLISION_CENTRAL, "bgk": L.FLAME_COLLISION_BGK}
 MAGNETIC = {"hall": L.FLAME_MAGNETIC_HALL, "emhd": L.FLAME_MAGNETIC_EMHD}
+FLUID_LATTICE = {"d3q27": L.FLAME_FLUID_D3Q27, "d3q19": L.FLAME_FLUID_D3Q19}
+MAGNETIC_LATTICE = {"d3q7": L.FLAME_MAGNETIC_D3Q7, "d3q15": L.FLAME_MAGNETIC_D3Q15, "d3q27": L.FLAME_MAGNETIC_D3Q27}
 
 
 def _ptr(t):
@@ -30,7 +32,10 @@ class Solver:
     force_u, force_b: (3, nz, ny, nx) static forcing (any float dtype; converted to the
     storage's arithmetic type: float64 for "f64", float32 otherwise), or None.
     collision: "central" (the paper's) or "bgk"; magnetic: "hall" (the paper's) or "emhd"
-    (electron MHD); the variants run forward only.
+    (electron MHD); fluid_lattice: "d3q27" (the paper's) or "d3q19" (with collision "bgk");
+    magnetic_lattice: "d3q7" (the paper's), "d3q15" or "d3q27"; the variants run forward only,
+    the lattice variants on the moment route. The canonical state then holds q fluid and m x 3
+    magnetic populations.
     placement_trials: the step's speed depends on the physical memory behind the population
     storage (at 512^3 FP32 one allocation runs at 9.1-9.4 ms per step, another of the same size
     and address at 10.5-10.8 ms: DRAM read latency at the L2 of about 2450 against 2800 cycles,
@@ -42,7 +47,7 @@ class Solver:
     def __init__(self, nx, ny, nz, nu, eta, d_i=0.0, b0=(0.0, 0.0, 0.0), storage="f32",
                  jmode="moment", layout="aa", u=None, b=None, grad_u=None, grad_b=None,
                  force_u=None, force_b=None, init_noneq=True, device="cuda", collision="central",
-                 magnetic="hall", placement_trials=1):
+                 magnetic="hall", placement_trials=1, fluid_lattice="d3q27", magnetic_lattice="d3q7"):
         if not torch.cuda.is_available():
             raise RuntimeError("flame needs a HIP device (torch.cuda.is_available() is False)")
         L.load()
@@ -60,6 +65,9 @@ class Solver:
         p.storage, p.jmode, p.layout = STORAGE[storage], JMODE[jmode], LAYOUT[layout]
         p.init_noneq = 1 if init_noneq else 0
         p.collision, p.magnetic = COLLISION[collision], MAGNETIC[magnetic]
+        p.fluid_lattice, p.magnetic_lattice = FLUID_LATTICE[fluid_lattice], MAGNETIC_LATTICE[magnetic_lattice]
+        self.q = L.FLUID_COUNT[p.fluid_lattice]
+        self.m = L.MAGNETIC_COUNT[p.magnetic_lattice]
         p.force_u = _ptr(self.force_u) or None
         p.force_b = _ptr(self.force_b) or None
         self.params = p
@@ -176,11 +184,13 @@ class Solver:
 
     # -- canonical state
     def get_populations(self, deviations=False):
-        """(f (27, nz, ny, nx), g (7, 3, nz, ny, nx)) float64 on device: full values, or the
-        departures from the rest state (the stored values, exactly) with deviations=True."""
-        out = torch.empty(48 * self.n, dtype=torch.float64, device=self.device)
+        """(f (q, nz, ny, nx), g (m, 3, nz, ny, nx)) float64 on device (q = 27, m = 7 on the
+        paper's velocity sets): full values, or the departures from the rest state (the stored
+        values, exactly) with deviations=True."""
+        q, m = self.q, self.m
+        out = torch.empty((q + 3 * m) * self.n, dtype=torch.float64, device=self.device)
         L.flame_get_populations(self.ctx, out.data_ptr(), int(deviations))
-        return out[: 27 * self.n].view(27, *self.shape), out[27 * self.n:].view(7, 3, *self.shape)
+        return out[: q * self.n].view(q, *self.shape), out[q * self.n:].view(m, 3, *self.shape)
 
     def set_populations(self, f, g, deviations=False):
         src = torch.cat([f.reshape(-1), g.reshape(-1)]).to(self.device, torch.float64).contiguous()
@@ -188,15 +198,15 @@ class Solver:
         self.stream.synchronize()
 
     def gather(self, cells, deviations=False):
-        """Canonical populations (k, 48) float64 at linear node indices ``cells``."""
+        """Canonical populations (k, q + 3 m) float64 at linear node indices ``cells``."""
         cells = torch.as_tensor(cells, dtype=torch.int64, device=self.device).contiguous()
-        out = torch.empty((cells.numel(), 48), dtype=torch.float64, device=self.device)
+        out = torch.empty((cells.numel(), self.q + 3 * self.m), dtype=torch.float64, device=self.device)
         L.flame_gather(self.ctx, cells.data_ptr(), cells.numel(), out.data_ptr(), int(deviations))
         return out
 
     def rest_populations(self):
         f, g = L.flame_rest_populations(self.params)
-        return (torch.tensor(f, dtype=torch.float64), torch.tensor(g, dtype=torch.float64).view(7, 3))
+        return (torch.tensor(f, dtype=torch.float64), torch.tensor(g, dtype=torch.float64).view(self.m, 3))
 
     def close(self):
         if getattr(self, "ctx", None):

@@ -1,6 +1,7 @@
 // Host build of the library's per-node arithmetic (test infrastructure): lets the CPU test
 // suite check the kernels' collision and its reverse pass against the oracle without a GPU.
 #include "../../paper_2212_11024_amd/csrc/flame_device.h"
+#include "../../paper_2212_11024_amd/csrc/flame_lattice.h"
 
 using namespace flame;
 
@@ -99,6 +100,43 @@ void hc_init_vjp(const double* u_in, const double* b_in, const double* G_in, con
     gu_out[a] = gu[a]; gb_out[a] = gb[a];
     for (int c = 0; c < 3; ++c) { gG_out[a * 3 + c] = gG[a][c]; gH_out[a * 3 + c] = gH[a][c]; }
   }
+}
+
+}  // extern "C"
+
+extern "C" {
+
+// One node's collision on a lattice variant, on deviations (the arithmetic of the variant step).
+// fq = 27 or 19 fluid velocities, mq = 7, 15 or 27 magnetic; params as for hc_collide.
+int hc_variant_collide(int fq, int mq, int bgk, int emhd, const double* f_in, const double* g_in, const double* Fin,
+                       const double* Sin, const double* params, double* f_out, double* g_out) {
+  const PhysConst<double> k = consts(params);
+  const double F[3] = {Fin[0], Fin[1], Fin[2]}, S[3] = {Sin[0], Sin[1], Sin[2]};
+  auto run = [&](auto fltag, auto mltag) {
+    using FL = decltype(fltag);
+    using ML = decltype(mltag);
+    double f[FL::q], g[ML::m * 3];
+    for (int i = 0; i < FL::q; ++i) f[i] = f_in[i];
+    for (int i = 0; i < ML::m * 3; ++i) g[i] = g_in[i];
+    if (bgk && emhd) lattice::variant_node<FL, ML, true, true>(f, g, F, S, k);
+    else if (bgk) lattice::variant_node<FL, ML, true, false>(f, g, F, S, k);
+    else if (emhd) lattice::variant_node<FL, ML, false, true>(f, g, F, S, k);
+    else lattice::variant_node<FL, ML, false, false>(f, g, F, S, k);
+    for (int i = 0; i < FL::q; ++i) f_out[i] = f[i];
+    for (int i = 0; i < ML::m * 3; ++i) g_out[i] = g[i];
+  };
+  auto by_mag = [&](auto fl) {
+    if (mq == 7) run(fl, lattice::Mag<7>{});
+    else if (mq == 15) run(fl, lattice::Mag<15>{});
+    else run(fl, lattice::Mag<27>{});
+  };
+  if (fq == 19) {
+    if (!bgk) return -1;
+    by_mag(lattice::Fluid<19>{});
+  } else {
+    by_mag(lattice::Fluid<27>{});
+  }
+  return 0;
 }
 
 }  // extern "C"

@@ -60,6 +60,8 @@ def _params(**kw):
     p.layout = kw.get("layout", L.FLAME_LAYOUT_AA)
     p.collision = kw.get("collision", L.FLAME_COLLISION_CENTRAL)
     p.magnetic = kw.get("magnetic", L.FLAME_MAGNETIC_HALL)
+    p.fluid_lattice = kw.get("fluid_lattice", L.FLAME_FLUID_D3Q27)
+    p.magnetic_lattice = kw.get("magnetic_lattice", L.FLAME_MAGNETIC_D3Q7)
     return p
 
 
@@ -71,6 +73,38 @@ def test_storage_bytes(lib):
     assert L.flame_storage_bytes(_params(storage=L.FLAME_F64)) == 48 * 8 * n
     assert L.flame_storage_bytes(_params(storage=L.FLAME_F16)) == 48 * 2 * n
     assert L.flame_storage_bytes(_params(shape=(512, 512, 512))) == 48 * 4 * 512 ** 3
+
+
+def test_lattice_variant_storage(lib):
+    """q + 3 m values per node (AA), twice that (AB); the combinations not built give 0."""
+    n = 8 * 8 * 8
+    bgk = L.FLAME_COLLISION_BGK
+    for fl, q in ((L.FLAME_FLUID_D3Q27, 27), (L.FLAME_FLUID_D3Q19, 19)):
+        for ml, m in ((L.FLAME_MAGNETIC_D3Q7, 7), (L.FLAME_MAGNETIC_D3Q15, 15), (L.FLAME_MAGNETIC_D3Q27, 27)):
+            kw = dict(fluid_lattice=fl, magnetic_lattice=ml, collision=bgk)
+            assert L.flame_storage_bytes(_params(**kw)) == (q + 3 * m) * 4 * n
+            assert L.flame_storage_bytes(_params(layout=L.FLAME_LAYOUT_AB, **kw)) == 2 * (q + 3 * m) * 4 * n
+            if (fl, ml) != (L.FLAME_FLUID_D3Q27, L.FLAME_MAGNETIC_D3Q7):
+                assert L.flame_storage_bytes(_params(jmode=L.FLAME_J_STENCIL, **kw)) == 0
+    assert L.flame_storage_bytes(_params(fluid_lattice=L.FLAME_FLUID_D3Q19)) == 0   # central-moment on D3Q19
+    assert L.flame_storage_bytes(_params(fluid_lattice=5)) == 0
+    assert L.flame_storage_bytes(_params(magnetic_lattice=3)) == 0
+
+
+def test_lattice_variant_rest_populations(lib):
+    """The rest state of the variants against the oracle's."""
+    from oracle import scheme
+    fnames = {L.FLAME_FLUID_D3Q27: "d3q27", L.FLAME_FLUID_D3Q19: "d3q19"}
+    mnames = {L.FLAME_MAGNETIC_D3Q15: "d3q15", L.FLAME_MAGNETIC_D3Q27: "d3q27"}
+    for fl, ml in ((L.FLAME_FLUID_D3Q19, L.FLAME_MAGNETIC_D3Q15), (L.FLAME_FLUID_D3Q27, L.FLAME_MAGNETIC_D3Q27)):
+        p = _params(fluid_lattice=fl, magnetic_lattice=ml, collision=L.FLAME_COLLISION_BGK)
+        p.b0[0], p.b0[1], p.b0[2] = 0.03, -0.02, 0.05
+        f, g = L.flame_rest_populations(p)
+        op = scheme.Params(1, 1, 1, 0.01, 0.01, 0.0, (0.03, -0.02, 0.05), collision="bgk",
+                           fluid_lattice=fnames[fl], magnetic_lattice=mnames[ml])
+        rest = scheme.rest_state(op)
+        assert max(abs(a - float(b)) for a, b in zip(f, rest.f.reshape(-1))) < 1e-17
+        assert max(abs(a - float(b)) for a, b in zip(g, rest.g.reshape(-1))) < 1e-17
 
 
 def test_model_variants_are_valid_parameters(lib):

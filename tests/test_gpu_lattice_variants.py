@@ -1,0 +1,173 @@
+"""GPU parity of the lattice variants (D3Q19 fluid with the BGK collision; D3Q15 and D3Q27
+magnetic sets) against the FP64 oracle, through the C ABI, on the moment route of J: initial
+states, odd and even step counts in both layouts (FP64), 100 steps in FP32, FP16 storage, AA
+against AB bit for bit, node fields, reductions and spectra, and the refusals of what is not built
+for them. The oracle's own FP64 rounding floor on these runs is the bar's scale: 1e-12 after 21
+steps, 2e-11 after 100 (the FP64 oracle against its extended-precision evaluation reaches a few
+1e-12 after 100 steps on the paper's lattices)."""
+
+import pytest
+import torch
+
+from oracle import diagnostics, scheme
+
+from parity_helpers import Case, deviation_error, gpu_solver, oracle_run
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    "d3q19": Case(13, 10, 9, jmode="moment", forced=True, seed=51, collision="bgk", fluid_lattice="d3q19"),
+    "d3q15": Case(13, 10, 9, jmode="moment", forced=True, seed=53, magnetic_lattice="d3q15"),
+    "d3q27m": Case(12, 8, 8, jmode="moment", seed=55, magnetic_lattice="d3q27", d_i=6.0),
+    "d3q19_d3q27_emhd": Case(11, 9, 8, jmode="moment", forced=True, seed=57, collision="bgk",
+                             fluid_lattice="d3q19", magnetic_lattice="d3q27", magnetic="emhd"),
+    # the BGK collision on D3Q27 with a magnetic variant, ragged rows longer than a block
+    "d3q15_bgk_long": Case(257, 3, 3, jmode="moment", seed=59, collision="bgk", magnetic_lattice="d3q15"),
+}
+
+
+def _print(name, **kw):
+    print(f"[lattice] {name} {kw}", flush=True)
+
+
+@pytest.mark.parametrize("layout", ["ab", "aa"])
+@pytest.mark.parametrize("name", list(CASES))
+def test_variant_initial_state(name, layout):
+    case = CASES[name]
+    _print(name, layout=layout, step=0)
+    s = gpu_solver(case, "f64", layout)
+    p, st = oracle_run(case, 0)
+    assert deviation_error(s, p, st) < 1e-14
+    s.close()
+
+
+@pytest.mark.parametrize("layout", ["ab", "aa"])
+@pytest.mark.parametrize("name", list(CASES))
+def test_variant_fp64_steps(name, layout):
+    case = CASES[name]
+    for steps in (21, 100):
+        _print(name, layout=layout, storage="f64", steps=steps)
+        s = gpu_solver(case, "f64", layout)
+        s.step(steps)
+        p, st = oracle_run(case, steps)
+        err = deviation_error(s, p, st)
+        print(f"[lattice] {name} {layout} f64 {steps} steps: {err:.3e}", flush=True)
+        assert err < (1e-12 if steps == 21 else 2e-11)
+        s.close()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_variant_fp32_100_steps(name):
+    case = CASES[name]
+    _print(name, storage="f32", steps=100)
+    p, st = oracle_run(case, 100, ftype=torch.float32)
+    s = gpu_solver(case, "f32", "aa")
+    s.step(100)
+    err = deviation_error(s, p, st)
+    print(f"[lattice] {name} f32 100 steps: {err:.3e}", flush=True)
+    assert err < 1e-5
+    s.close()
+
+
+@pytest.mark.parametrize("name", ["d3q19", "d3q15", "d3q27m"])
+def test_variant_fp16_storage(name):
+    """FP16 deviation storage with FP32 arithmetic (exact power-of-two scales per velocity
+    class): 50 steps against the FP64 oracle, the FP16 bar of the paper's lattices (5e-3)."""
+    case = CASES[name]
+    _print(name, storage="f16", steps=50)
+    p, st = oracle_run(case, 50, ftype=torch.float32)
+    s = gpu_solver(case, "f16", "aa")
+    s.step(50)
+    err = deviation_error(s, p, st)
+    print(f"[lattice] {name} f16 50 steps: {err:.3e}", flush=True)
+    assert err < 5e-3
+    s.close()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+@pytest.mark.parametrize("name", ["d3q19", "d3q27m"])
+def test_variant_aa_equals_ab_bitwise(name, storage):
+    case = CASES[name]
+    _print("aa-vs-ab", case=name, storage=storage)
+    a = gpu_solver(case, storage, "aa")
+    b = gpu_solver(case, storage, "ab")
+    for n in (1, 4, 7):
+        a.step(n)
+        b.step(n)
+        fa, ga = a.get_populations()
+        fb, gb = b.get_populations()
+        assert torch.equal(fa, fb) and torch.equal(ga, gb)
+    a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("name", ["d3q19", "d3q15"])
+def test_variant_fields_reductions_spectra(name):
+    case = CASES[name]
+    _print("diagnostics", case=name)
+    p, st = oracle_run(case, 9)
+    s = gpu_solver(case, "f64", "aa")
+    s.step(9)
+    rho, u, B, J, d = [t.cpu() for t in s.fields()]
+    orho, ou, oB, oJ, od = scheme.fields(st, p)
+    for a, b in ((rho, orho), (u, ou), (B, oB), (J, oJ), (d, od)):
+        assert (a - b).abs().max() <= 1e-12 * max(1e-3, float(b.abs().max()))
+    r = s.reduce()
+    ro = diagnostics.reductions(st, p)
+    assert torch.allclose(r[:10], ro[:10], rtol=1e-11, atol=1e-18)
+    assert (r[10:] - ro[10:]).abs().max() < 1e-12 * float(ro[9])
+    ns = diagnostics.max_shell(p.shape)
+    for field, ref in (("u", ou), ("B", oB)):
+        e = s.spectrum(field, ns)
+        eo = torch.tensor(diagnostics.spectrum(ref, ns))
+        assert torch.allclose(e, eo, rtol=1e-10, atol=1e-20 + 1e-12 * float(eo.max()))
+    # checkpoint / resume through deviation copies, and gather, on the variant layout
+    f, g = s.get_populations(deviations=True)
+    t = gpu_solver(case, "f64", "aa")
+    t.set_populations(f, g, deviations=True)
+    f2, g2 = t.get_populations(deviations=True)
+    assert torch.equal(f, f2) and torch.equal(g, g2)
+    cells = torch.tensor([0, 5, s.n - 1, s.n + 3], dtype=torch.int64)
+    rows = s.gather(cells, deviations=True).cpu()
+    q, m = s.q, s.m
+    assert rows.shape == (4, q + 3 * m)
+    flat_f, flat_g = f.reshape(q, -1).cpu(), g.reshape(m * 3, -1).cpu()
+    for k, cell in enumerate(cells[:3].tolist()):
+        assert torch.equal(rows[k, :q], flat_f[:, cell]) and torch.equal(rows[k, q:], flat_g[:, cell])
+    assert bool(torch.isnan(rows[3]).all())
+    s.close()
+    t.close()
+
+
+def test_variant_refusals():
+    """Combinations not built are refused before any device work: a lattice variant on the stencil
+    route, D3Q19 with the central-moment collision (FLAME_E_UNSUPPORTED from flame_init, 0 bytes
+    from flame_storage_bytes); reverse mode and trace lattices on a variant context."""
+    import ctypes
+    from paper_2212_11024_amd import _lib as L
+    lib = L.load()
+    for kw in ({"fluid_lattice": L.FLAME_FLUID_D3Q19, "collision": L.FLAME_COLLISION_CENTRAL},
+               {"magnetic_lattice": L.FLAME_MAGNETIC_D3Q15, "jmode": L.FLAME_J_STENCIL}):
+        p = L.flame_params()
+        p.nx = p.ny = p.nz = 8
+        p.nu = p.eta = 0.01
+        p.storage, p.layout = L.FLAME_F32, L.FLAME_LAYOUT_AA
+        for k, v in kw.items():
+            setattr(p, k, v)
+        assert lib.flame_storage_bytes(ctypes.byref(p)) == 0
+        u = torch.zeros((3, 8, 8, 8), dtype=torch.float64, device="cuda")
+        buf = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")
+        ctx = ctypes.c_void_p()
+        code = lib.flame_init(ctypes.byref(p), u.data_ptr(), u.data_ptr(), None, None, buf.data_ptr(), 1 << 20,
+                              None, ctypes.byref(ctx))
+        assert code == L.FLAME_E_UNSUPPORTED and not ctx.value
+    s = gpu_solver(CASES["d3q19"], "f32", "aa")
+    assert L.flame_trace_bytes(s.ctx) == 0
+    lam = torch.empty(64 * s.n, dtype=torch.float32, device="cuda")
+    for call in (lambda: L.flame_step_save(s.ctx, lam.data_ptr()),
+                 lambda: L.flame_trace_export(s.ctx, lam.data_ptr()),
+                 lambda: L.flame_adjoint_fields(s.ctx, 0, 0, lam.data_ptr())):
+        with pytest.raises(L.FlameError) as e:
+            call()
+        assert e.value.code == L.FLAME_E_UNSUPPORTED
+    s.close()

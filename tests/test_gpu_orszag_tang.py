@@ -94,6 +94,14 @@ def test_turbulence_summary_matches_its_parts():
     assert t["E_kin"] == float(red[0]) and t["E_mag"] == float(red[1])
     assert abs(t["eps"] / eps - 1) < 1e-12 and abs(t["integral_scale"] / scale - 1) < 1e-12
     assert abs(t["Re"] - math.sqrt(2 * float(red[0])) * scale / 0.01) < 1e-9 * t["Re"]
+    # against the oracle's summary of the same run (its fields after the same 50 steps)
+    from oracle import diagnostics, scheme
+    p = scheme.Params(n, n, n, 0.01, 0.02, 0.5, (0.0, 0.0, 0.0), "moment", "closed")
+    st = scheme.step(scheme.init_state(p, u.cpu(), b.cpu(), gu.cpu(), gb.cpu()), p, 50)
+    _, ou, oB, _, _ = scheme.fields(st, p)
+    ref = diagnostics.turbulence_summary(ou, oB, 0.01, 0.02)
+    for key in ("E_kin", "E_mag", "eps", "u_rms", "integral_scale", "Re"):
+        assert abs(t[key] - ref[key]) <= 1e-10 * abs(ref[key]), (key, t[key], ref[key])
     # the Orszag-Tang velocity lives in shell 1 at t = 0: L is the box
     s0 = Solver(n, n, n, 0.01, 0.02, 0.5, (0.0, 0.0, 0.0), "f64", "moment", "aa", u, b, gu, gb)
     assert abs(s0.turbulence()["integral_scale"] - n) < 1e-9 * n

@@ -119,6 +119,31 @@ def test_run_to_run_determinism():
     assert torch.equal(a.reduce(), b.reduce())
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+def test_launch_shape_independence(storage, monkeypatch):
+    """The state does not depend on the launch shape, bit for bit: the planes per workgroup of the
+    curl-stencil kernel (FLAME_ZCHUNK_PLANES: the built-in 32, 5 with a ragged last chunk, 1, the
+    whole column and more than it) and the threads per row block of the node-local kernels
+    (FLAME_ROW_THREADS: one block per row, or 64, 128 and 192 threads, so that a 257-node row
+    spans several blocks with a ragged last one), on forced runs over 7 steps (both AA parities)."""
+    cases = [(Case(13, 10, 37, jmode="stencil", forced=True, seed=61), "FLAME_ZCHUNK_PLANES", ["0", "5", "1", "37", "64"]),
+             (Case(257, 3, 4, jmode="moment", forced=True, seed=63), "FLAME_ROW_THREADS", ["0", "64", "128", "192"])]
+    for case, var, values in cases:
+        ref = None
+        for v in values:
+            monkeypatch.setenv(var, v)
+            _print_case("launch shape", storage=storage, jmode=case.jmode, **{var: v})
+            s = gpu_solver(case, storage, "aa")
+            s.step(7)
+            f, g = s.get_populations(deviations=True)
+            s.close()
+            if ref is None:
+                ref = (f, g)
+            else:
+                assert torch.equal(f, ref[0]) and torch.equal(g, ref[1]), (var, v)
+        monkeypatch.delenv(var)
+
+
 @pytest.mark.parametrize("shape", [(13, 10, 9), (48, 40, 36)])
 def test_spectra_are_bitwise_reproducible(shape):
     """Shell spectra, dissipation spectra and the energy-transfer terms sum in a fixed order (no

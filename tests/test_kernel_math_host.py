@@ -33,6 +33,7 @@ def hc(tmp_path_factory):
     I = ctypes.POINTER(ctypes.c_int)
     lib.hc_init.argtypes = [D] * 7 + [I, D, D]
     lib.hc_init_vjp.argtypes = [D] * 6 + [I] + [D] * 6
+    lib.hc_variant_collide.argtypes = [ctypes.c_int] * 4 + [D] * 7
     return lib
 
 
@@ -165,3 +166,40 @@ def test_initial_state_and_its_reverse_pass(hc, flags):
         for (arr, _), ref in zip(outs, grads):
             ref = np.zeros(arr.size) if ref is None else ref.numpy().reshape(-1)
             assert np.abs(arr - ref).max() < 1e-12 * max(1.0, np.abs(ref).max())
+
+
+@pytest.mark.parametrize("fl,ml,coll,mag", [("d3q19", "d3q7", "bgk", "hall"), ("d3q27", "d3q15", "central", "hall"),
+                                            ("d3q27", "d3q27", "bgk", "emhd"), ("d3q19", "d3q27", "bgk", "emhd"),
+                                            ("d3q19", "d3q15", "bgk", "hall")])
+def test_variant_collision_matches_oracle(hc, fl, ml, coll, mag):
+    """The lattice variants' node update (moments, J from the magnetic moments, fluid and magnetic
+    collisions, forcing), compiled for the host from the kernels' header, against the oracle's
+    collision of the same node."""
+    from oracle.lattice import FLUID_LATTICES, MAGNETIC_LATTICES
+    rng = np.random.default_rng(hash((fl, ml, coll, mag)) % 2 ** 32)
+    flat, mlat = FLUID_LATTICES[fl], MAGNETIC_LATTICES[ml]
+    for trial in range(5):
+        nu, eta, d_i = rng.uniform(0.005, 0.05), rng.uniform(0.005, 0.05), rng.uniform(0.0, 6.0)
+        b0 = rng.normal(0, 0.05, 3)
+        F = rng.normal(0, 1e-4, 3)
+        S = rng.normal(0, 1e-4, 3)
+        p = scheme.Params(1, 1, 1, nu, eta, d_i, tuple(b0), "moment", "closed",
+                          torch.tensor(F).view(3, 1, 1, 1), torch.tensor(S).view(3, 1, 1, 1), collision=coll,
+                          magnetic=mag, fluid_lattice=fl, magnetic_lattice=ml)
+        rest = scheme.rest_state(p)
+        U = torch.tensor(rng.normal(0, 0.04, 3)).view(3, 1)
+        B = torch.tensor(b0 + rng.normal(0, 0.05, 3)).view(3, 1)
+        f = equilibrium.f_mhd_eq_lattice(torch.ones(1, dtype=torch.float64), U, B, flat)[:, 0].numpy()
+        f = f + rng.normal(0, 2e-4, flat.q)
+        g = (mlat.w.view(-1, 1) * B.view(1, 3)).numpy() + rng.normal(0, 3e-3, (mlat.q, 3))
+        st = scheme.State(torch.tensor(f).view(flat.q, 1, 1, 1), torch.tensor(g).view(mlat.q, 3, 1, 1, 1))
+        want = scheme.collide(st, p)
+        kp = np.array([omega_fluid(nu), omega_magnetic(eta), d_i, *b0])
+        fo = np.zeros(flat.q)
+        go = np.zeros(mlat.q * 3)
+        args = [_p(f - rest.f.reshape(-1).numpy())[1], _p(g.reshape(-1) - rest.g.reshape(-1).numpy())[1],
+                _p(F)[1], _p(S)[1], _p(kp)[1], fo.ctypes.data_as(D), go.ctypes.data_as(D)]
+        assert hc.hc_variant_collide(flat.q, mlat.q, int(coll == "bgk"), int(mag == "emhd"), *args) == 0
+        df = fo + rest.f.reshape(-1).numpy() - want.f.reshape(-1).numpy()
+        dg = go + rest.g.reshape(-1).numpy() - want.g.reshape(-1).numpy()
+        assert np.abs(df).max() < 1e-15 and np.abs(dg).max() < 1e-15, (trial, np.abs(df).max(), np.abs(dg).max())

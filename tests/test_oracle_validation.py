@@ -63,3 +63,35 @@ def test_viscosity_error_recovers_the_damping(excess):
     t = np.arange(0.0, 4000.0, 0.5)
     eps = V.viscosity_error(t, _damped(t, 1e-3, g, 2 * math.pi / 389.0), k, nu, 8)
     assert abs(eps - excess) < 1e-6
+
+
+def test_turbulence_summary_closed_forms():
+    """The turbulence summary of Sec. 4.4 on fields with closed-form answers: a single sine mode
+    of shell s gives L = n / s, eps = nu a^2 q^2 / 2 with q = 2 pi s / n, E_kin = a^2 / 4 and
+    Re = (a / sqrt 2) L / nu; two modes of energies E1 (shell 1) and E2 (shell 2) give
+    L = n (E1 + E2 / 2) / (E1 + E2); B's energy is measured from b0."""
+    import math
+
+    import torch
+
+    from oracle import diagnostics as D
+    n, nu, eta = 16, 0.01, 0.02
+    x = torch.arange(n, dtype=torch.float64)
+    for s in (1, 3):
+        a = 0.03
+        u = torch.zeros(3, n, n, n, dtype=torch.float64)
+        u[1] = a * torch.sin(2 * math.pi * s * x / n).view(1, 1, n)
+        B = torch.zeros_like(u)
+        B[2] += 0.1
+        t = D.turbulence_summary(u, B, nu, eta, b0=(0.0, 0.0, 0.1))
+        q = 2 * math.pi * s / n
+        assert abs(t["integral_scale"] - n / s) < 1e-12 * n
+        assert abs(t["eps"] - nu * a * a * q * q / 2) < 1e-12 * nu * a * a * q * q
+        assert abs(t["E_kin"] - a * a / 4) < 1e-15 and t["E_mag"] == 0.0
+        assert abs(t["Re"] - (a / math.sqrt(2)) * (n / s) / nu) < 1e-9 * t["Re"]
+    a1, a2 = 0.02, 0.05
+    u = torch.zeros(3, n, n, n, dtype=torch.float64)
+    u[0] = (a1 * torch.cos(2 * math.pi * x / n)).view(1, n, 1) + (a2 * torch.sin(4 * math.pi * x / n)).view(n, 1, 1)
+    e1, e2 = a1 * a1 / 4, a2 * a2 / 4
+    t = D.turbulence_summary(u, torch.zeros_like(u), nu, eta)
+    assert abs(t["integral_scale"] - n * (e1 + e2 / 2) / (e1 + e2)) < 1e-12 * n
