@@ -199,6 +199,19 @@ flame_status flame_moments(flame_ctx* c, double* rho, double* u, double* b, doub
  * block partials: bitwise reproducible for a given grid and state. */
 flame_status flame_reduce(flame_ctx* c, double* out);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the reductions of flame_reduce, computed by the same
+ * kernels in the same fixed order (bitwise the same values), into a caller-owned device buffer
+ * out[FLAME_NRED] (double), asynchronously on the context's stream. Allocates nothing and does
+ * not synchronise: the block partials go to a static device array of 2048 x FLAME_NRED doubles
+ * (256 KiB per GPU, held until the process ends), which covers every grid (the reduction visits
+ * the nodes with at most 2048 blocks). Calls on one GPU share that array and leave their partials
+ * in it: calls that may overlap on one GPU (several streams or contexts) race and must be
+ * ordered by the caller. There is no status for a blown-up state: slot 8 counts non-finite nodes
+ * and slot 6 holds max|u| (FLAME_E_UNSTABLE at c_s = 1/sqrt(3) in flame_reduce).
+ * FLAME_E_INVAL for a NULL out. */
+flame_status flame_reduce_noalloc(flame_ctx* c, double* out);
+
 /* Shell energy spectrum of u (field = 0) or B (field = 1) into host e_k[nshells]:
  * E(s) = 1/2 sum_{round(|k|) = s} |v_hat(k)|^2, v_hat = DFT(v) / ncell, k the signed integer
  * wavevector (paper Sec. 4.4 spectra). FP64 FFT (hipFFT) and binning in a fixed order (no

@@ -57,6 +57,7 @@ _SIGNATURES = {
     "flame_step": (ctypes.c_int32, [_P, ctypes.c_int64]),
     "flame_moments": (ctypes.c_int32, [_P, _P, _P, _P, _P, _P]),
     "flame_reduce": (ctypes.c_int32, [_P, ctypes.POINTER(ctypes.c_double)]),
+    "flame_reduce_noalloc": (ctypes.c_int32, [_P, _P]),
     "flame_spectrum": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
     "flame_dissipation_spectrum": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32,
                                                     ctypes.POINTER(ctypes.c_double)]),
@@ -152,6 +153,11 @@ def flame_reduce(ctx: int, allow_nonfinite: bool = False):
     if not (allow_nonfinite and code in (FLAME_E_NONFINITE, FLAME_E_UNSTABLE)):
         _check(code, ctx)
     return code, list(out)
+
+
+def flame_reduce_noalloc(ctx: int, out: int) -> int:
+    """Reductions into the device buffer out (double [FLAME_NRED]); asynchronous, allocates nothing."""
+    return _check(load().flame_reduce_noalloc(ctx, out), ctx)
 
 
 def flame_spectrum(ctx: int, field: int, nshells: int):

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -437,6 +438,15 @@ __global__ __launch_bounds__(64) void reduce_merge_kernel(const double* partials
   out[k] = acc;
 }
 
+}  // namespace flame
+
+// Block partials of the allocation-free reductions (flame_reduce_noalloc): one row of FLAME_NRED
+// doubles per reduction block, kRedBlocksMax rows (256 KiB). Each GPU the library runs on holds its
+// own copy until the process ends; host code reaches it only through the address that
+// hipGetSymbolAddress returns for the current device (see scratch_address), never by this name.
+static __device__ __align__(256) double scratch[flame::kRedBlocksMax * FLAME_NRED];
+
+namespace flame {
 
 // ------------------------------------------------------------------ spectra
 template <typename S>
@@ -800,6 +810,25 @@ __global__ void max_field_kernel(const double* b, double b0x, double b0y, double
   if (threadIdx.x == 0) out[blockIdx.x] = sh[0];
 }
 
+// Device address of this device's copy of the scratch array, looked up once per device (with that
+// device current) and kept for the process.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+double* g_scratch_addr[kMaxDevices] = {};
+
+hipError_t scratch_address(int device, double** out) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_addr[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_addr[device] = static_cast<double*>(ptr);
+  }
+  *out = g_scratch_addr[device];
+  return hipSuccess;
+}
+
 // Lattice sound speed c_s = 1/sqrt(3): the flame_reduce guard on max |u|.
 constexpr double kSoundSpeed = 0.57735026918962576;
 
@@ -924,6 +953,13 @@ flame_status flame_init(const flame_params* p, const double* u, const double* b,
     c->err = "hipGetDevice failed (no HIP device?)";
     return bail(FLAME_E_HIP);
   }
+  {
+    const hipError_t e = scratch_address(c->device, &c->scratch);
+    if (e != hipSuccess) {
+      c->err = std::string("hipGetSymbolAddress of the reduction scratch: ") + hipGetErrorString(e);
+      return bail(FLAME_E_HIP);
+    }
+  }
   c->red_blocks = static_cast<int>(std::min<size_t>(kRedBlocksMax, blocks_for(c->n, kRedThreads)));
   // block partials of the reductions plus one row for their merged results
   if (hipMalloc(&c->red_partials, sizeof(double) * FLAME_NRED * (std::max(c->red_blocks, 1) + 1)) != hipSuccess) {
@@ -1021,6 +1057,17 @@ flame_status flame_reduce(flame_ctx* c, double* out) {
   if (out[8] > 0) return fail(c, FLAME_E_NONFINITE, "non-finite populations at " + std::to_string(out[8]) + " nodes");
   if (out[6] >= kSoundSpeed)
     return fail(c, FLAME_E_UNSTABLE, "max |u| = " + std::to_string(out[6]) + " reached the lattice sound speed");
+  return FLAME_OK;
+}
+
+flame_status flame_reduce_noalloc(flame_ctx* c, double* out) {
+  if (!c || !out) return c ? fail(c, FLAME_E_INVAL, "out is NULL") : FLAME_E_INVAL;
+  if (!c->scratch) return fail(c, FLAME_E_HIP, "the reduction scratch of this device was not found at init");
+  if (c->red_blocks < 1 || c->red_blocks > kRedBlocksMax)
+    return fail(c, FLAME_E_INVAL, "reduction needs " + std::to_string(c->red_blocks) +
+                                      " block partials; the static scratch holds " + std::to_string(kRedBlocksMax));
+  const hipError_t e = launch_reduce(c, c->scratch, out);
+  if (e != hipSuccess) return fail(c, FLAME_E_HIP, std::string("reduce kernel: ") + hipGetErrorString(e));
   return FLAME_OK;
 }
 

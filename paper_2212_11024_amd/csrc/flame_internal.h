@@ -32,6 +32,7 @@ struct flame_ctx {
   // library-owned scratch
   double* red_partials = nullptr;
   int red_blocks = 0;
+  double* scratch = nullptr;   // this device's static reduction scratch (not owned)
   double* spec_real = nullptr;
   void* spec_cplx = nullptr;
   double* spec_partials = nullptr;
