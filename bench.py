@@ -43,11 +43,11 @@ HBM_PEAK_GBPS = 8000.0        # MI355X HBM3E peak
 # a plain copy (see the traffic summary named below). Valid only for the kernel source it was
 # measured on: reported as null once the fingerprint of the kernel sources changes.
 TRAFFIC_RECORDS = {
-    ("f32", "moment"): {"fingerprint": "845b728891c4796b", "GB_per_launch": 55.3,
+    ("f32", "moment"): {"fingerprint": "054fea12b9f4e14d", "GB_per_launch": 55.3,
                         "profile": "profiles/traffic_step_f32_moment_512.md"},
-    ("f32", "stencil"): {"fingerprint": "845b728891c4796b", "GB_per_launch": 69.2,
+    ("f32", "stencil"): {"fingerprint": "054fea12b9f4e14d", "GB_per_launch": 65.2,
                          "profile": "profiles/traffic_step_f32_stencil_512.md"},
-    ("f64", "moment"): {"fingerprint": "845b728891c4796b", "GB_per_launch": 110.3,
+    ("f64", "moment"): {"fingerprint": "054fea12b9f4e14d", "GB_per_launch": 110.3,
                         "profile": "profiles/traffic_step_f64_moment_512.md"},
 }
 
@@ -411,9 +411,26 @@ def copy_probe(gib=4, reps=5):
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    # a read-only and a write-only pass over the same bytes (torch's sum and fill): second
+    # calibration points for the traffic counters; event-timed per call, launch gaps included
+    read_ms = timed(lambda: a.sum())
+    fill_ms = timed(lambda: b.fill_(2.0))
     del a, b
     torch.cuda.empty_cache()
-    return {"bytes_each_way": gib * (1 << 30), "ms": round(ms, 4), "GBps": round(2 * gib * (1 << 30) / (ms * 1e6), 1)}
+    nbytes = gib * (1 << 30)
+    return {"bytes_each_way": nbytes, "ms": round(ms, 4), "GBps": round(2 * nbytes / (ms * 1e6), 1),
+            "torch_sum_GBps": round(nbytes / (read_ms * 1e6), 1), "torch_fill_GBps": round(nbytes / (fill_ms * 1e6), 1)}
 
 
 def cpu_baseline(seconds=15.0):
