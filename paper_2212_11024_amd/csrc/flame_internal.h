@@ -28,6 +28,7 @@ struct flame_ctx {
   // the node-local kernels (0: the row rounded up to whole wavefronts, at most 256)
   int zchunk = 0;
   int row_tx = 0;
+  bool global_addr = false;   // FLAME_GLOBAL_ADDRESSING=1: no buffer addressing in the step
   std::string err;
   // library-owned scratch
   double* red_partials = nullptr;
@@ -68,6 +69,16 @@ inline size_t population_stride(const flame_params& p) {
   const size_t n = static_cast<size_t>(p.nx) * p.ny * p.nz;
   const size_t align = 256 / vb;
   return (n + align - 1) / align * align + FLAME_STRIDE_PAD_BYTES / vb;
+}
+// The node-local step addresses its arrays through buffer resources (32-bit offsets, range
+// limit 2^32 - 1 bytes) when every population and forcing array ends at least 16 bytes below
+// 4 GiB, so that no access can meet the range limit whichever byte of it the hardware checks;
+// arrays of exactly 4 GiB (FP32 at 2^30 nodes) take the 64-bit global addresses instead.
+inline bool buffer_addressing_ok(const flame_params& p) {
+  const size_t limit = (size_t(1) << 32) - 16;
+  const size_t n = static_cast<size_t>(p.nx) * p.ny * p.nz;
+  const size_t arith = p.storage == FLAME_F64 ? 8 : 4;
+  return population_stride(p) * value_bytes(p.storage) <= limit && n * arith <= limit;
 }
 // Model bits of the step kernels: 1 = BGK fluid collision, 2 = electron MHD; 0 is the paper's.
 inline int step_model(const flame_params& p) {

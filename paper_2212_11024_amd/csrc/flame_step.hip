@@ -13,7 +13,8 @@
 //
 // Two kernels:
 //   step_local  - moment-route J: every node independent, one node per thread, rows of up to
-//     256 nodes per block.
+//     256 nodes per block; arrays addressed through buffer resources when every array ends at
+//     least 16 bytes below 4 GiB, else through 64-bit global addresses (bitwise the same step).
 //   step_zmarch - stencil J: a workgroup owns a 64 x 4 tile of (x, y) and marches along z. It
 //     keeps the field fluctuation b of three consecutive planes in LDS (computed once per node
 //     from that node's own magnetic populations, which it holds in registers for the next
@@ -59,9 +60,32 @@ struct Rows {
   __device__ __forceinline__ uint32_t at(int dx, int dy) const { return r[dx + 1][dy + 1]; }
 };
 
+// Addressing of the population and forcing arrays. Every array spans at most 4 GiB (checked at
+// init), so an access is a wave-uniform array base plus a 32-bit per-lane byte offset. Global:
+// 64-bit flat-global addresses formed per access in vector registers. Buffer: a buffer resource
+// per array (base in scalar registers, no range limit below 4 GiB, raw addressing) and the 32-bit
+// offset as the only per-lane operand, which takes the 64-bit address arithmetic off the vector
+// ALU (about 140 of the node-local step's 1240 vector instructions per node at FP16 storage).
+enum class Addr { Global, Buffer };
+typedef unsigned int U32x2 __attribute__((ext_vector_type(2)));
 template <typename S>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc_of(const S* base) {
+  // stride 0, num_records 2^32 - 1, dword 3 of a raw 32-bit-format buffer on gfx9
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<S*>(base), 0, 0xFFFFFFFF, 0x00020000);
+}
+template <Addr A, typename S>
 __device__ __forceinline__ S ld(const S* base, uint32_t off) {
-  return *reinterpret_cast<const S*>(reinterpret_cast<const char*>(base) + off * static_cast<uint32_t>(sizeof(S)));
+  const uint32_t vo = off * static_cast<uint32_t>(sizeof(S));
+  if constexpr (A == Addr::Buffer) {
+    if constexpr (sizeof(S) == 2)
+      return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b16(rsrc_of(base), vo, 0, 0));
+    else if constexpr (sizeof(S) == 4)
+      return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b32(rsrc_of(base), vo, 0, 0));
+    else
+      return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b64(rsrc_of(base), vo, 0, 0));
+  } else {
+    return *reinterpret_cast<const S*>(reinterpret_cast<const char*>(base) + vo);
+  }
 }
 // Stencil kernel: compute the ring of b around the tile one plane ahead, together with the
 // tile's own loads of that plane (the ring nodes' populations are the ones the neighbouring
@@ -72,13 +96,24 @@ __device__ __forceinline__ S ld(const S* base, uint32_t off) {
 #ifndef FLAME_NT_STORES
 #define FLAME_NT_STORES 1
 #endif
-template <typename S>
+template <Addr A, typename S>
 __device__ __forceinline__ void st(S* base, uint32_t off, S v) {
-  S* p = reinterpret_cast<S*>(reinterpret_cast<char*>(base) + off * static_cast<uint32_t>(sizeof(S)));
-  if (FLAME_NT_STORES)
-    __builtin_nontemporal_store(v, p);
-  else
-    *p = v;
+  const uint32_t vo = off * static_cast<uint32_t>(sizeof(S));
+  if constexpr (A == Addr::Buffer) {
+    constexpr int aux = FLAME_NT_STORES ? 2 : 0;   // 2: the non-temporal hint
+    if constexpr (sizeof(S) == 2)
+      __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(short, v), rsrc_of(base), vo, 0, aux);
+    else if constexpr (sizeof(S) == 4)
+      __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, v), rsrc_of(base), vo, 0, aux);
+    else
+      __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U32x2, v), rsrc_of(base), vo, 0, aux);
+  } else {
+    S* p = reinterpret_cast<S*>(reinterpret_cast<char*>(base) + vo);
+    if (FLAME_NT_STORES)
+      __builtin_nontemporal_store(v, p);
+    else
+      *p = v;
+  }
 }
 
 // Plane offsets of z - 1, z, z + 1 (periodic), uniform across the workgroup.
@@ -93,7 +128,7 @@ struct Planes {
 };
 
 // Fluid populations of the node. FAA: in place (PAR selects the AA step); else pull.
-template <typename S, bool FAA, int PAR>
+template <typename S, bool FAA, int PAR, Addr A = Addr::Global>
 __device__ __forceinline__ void load_fluid(const StepArgs<S>& a, const Rows& rw, const Planes& pl,
                                            typename Enc<S>::R (&f)[kQ]) {
   using E = Enc<S>;
@@ -103,11 +138,11 @@ __device__ __forceinline__ void load_fluid(const StepArgs<S>& a, const Rows& rw,
     const bool own = FAA && PAR == 0;
     const uint32_t off = own ? rw.at(0, 0) + pl.at(0) : rw.at(-cq(i, 0), -cq(i, 1)) + pl.at(-cq(i, 2));
     const S* base = a.f_src + static_cast<size_t>(FAA && PAR == 1 ? oppq(i) : i) * a.stride;
-    f[i] = E::dec(ld(base, off), R(1.0 / E::fscale(i)));
+    f[i] = E::dec(ld<A>(base, off), R(1.0 / E::fscale(i)));
   }
 }
 
-template <typename S, bool FAA, int PAR>
+template <typename S, bool FAA, int PAR, Addr A = Addr::Global>
 __device__ __forceinline__ void store_fluid(const StepArgs<S>& a, const Rows& rw, const Planes& pl,
                                             const typename Enc<S>::R (&f)[kQ]) {
   using E = Enc<S>;
@@ -117,11 +152,11 @@ __device__ __forceinline__ void store_fluid(const StepArgs<S>& a, const Rows& rw
     const bool shifted = FAA && PAR == 1;
     const uint32_t off = shifted ? rw.at(cq(i, 0), cq(i, 1)) + pl.at(cq(i, 2)) : rw.at(0, 0) + pl.at(0);
     S* base = a.f_dst + static_cast<size_t>(FAA && PAR == 0 ? oppq(i) : i) * a.stride;
-    st(base, off, E::enc(f[i], R(E::fscale(i))));
+    st<A>(base, off, E::enc(f[i], R(E::fscale(i))));
   }
 }
 
-template <typename S, bool MAA, int PAR>
+template <typename S, bool MAA, int PAR, Addr A = Addr::Global>
 __device__ __forceinline__ void load_magnetic(const StepArgs<S>& a, const Rows& rw, const Planes& pl,
                                               typename Enc<S>::R (&g)[kM]) {
   using E = Enc<S>;
@@ -133,12 +168,12 @@ __device__ __forceinline__ void load_magnetic(const StepArgs<S>& a, const Rows& 
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const S* base = a.g_src + static_cast<size_t>((MAA && PAR == 1 ? oppm(i) : i) * 3 + c) * a.stride;
-      g[i * 3 + c] = E::dec(ld(base, off), R(1.0 / E::mscale(i)));
+      g[i * 3 + c] = E::dec(ld<A>(base, off), R(1.0 / E::mscale(i)));
     }
   }
 }
 
-template <typename S, bool MAA, int PAR>
+template <typename S, bool MAA, int PAR, Addr A = Addr::Global>
 __device__ __forceinline__ void store_magnetic(const StepArgs<S>& a, const Rows& rw, const Planes& pl,
                                                const typename Enc<S>::R (&g)[kM]) {
   using E = Enc<S>;
@@ -150,19 +185,19 @@ __device__ __forceinline__ void store_magnetic(const StepArgs<S>& a, const Rows&
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       S* base = a.g_dst + static_cast<size_t>((MAA && PAR == 0 ? oppm(i) : i) * 3 + c) * a.stride;
-      st(base, off, E::enc(g[i * 3 + c], R(E::mscale(i))));
+      st<A>(base, off, E::enc(g[i * 3 + c], R(E::mscale(i))));
     }
   }
 }
 
-template <typename S>
+template <typename S, Addr A = Addr::Global>
 __device__ __forceinline__ void forcing_at(const StepArgs<S>& a, uint32_t cell, typename Enc<S>::R (&F)[3],
                                            typename Enc<S>::R (&Sb)[3]) {
   using R = typename Enc<S>::R;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    F[c] = a.force_u ? ld(a.force_u + static_cast<size_t>(c) * a.n, cell) : R(0);
-    Sb[c] = a.force_b ? ld(a.force_b + static_cast<size_t>(c) * a.n, cell) : R(0);
+    F[c] = a.force_u ? ld<A>(a.force_u + static_cast<size_t>(c) * a.n, cell) : R(0);
+    Sb[c] = a.force_b ? ld<A>(a.force_b + static_cast<size_t>(c) * a.n, cell) : R(0);
   }
 }
 
@@ -216,7 +251,7 @@ __device__ __forceinline__ void save_current(R* save, size_t n, uint32_t cell, c
 // ------------------------------------------------------------------ moment-route kernel
 constexpr int kLocalThreads = 256;
 
-template <typename S, bool FAA, bool MAA, int PAR, bool SAVE, int MODEL>
+template <typename S, bool FAA, bool MAA, int PAR, bool SAVE, int MODEL, Addr A>
 __global__ __launch_bounds__(kLocalThreads) void step_local(StepArgs<S> a) {
   using R = typename Enc<S>::R;
   unsigned bx, by, bz;
@@ -229,10 +264,10 @@ __global__ __launch_bounds__(kLocalThreads) void step_local(StepArgs<S> a) {
   const Planes pl(z, a.nz, static_cast<uint32_t>(a.nx) * a.ny);
   const uint32_t cell = rw.at(0, 0) + pl.at(0);
   R f[kQ], g[kM];
-  load_fluid<S, FAA, PAR>(a, rw, pl, f);
-  load_magnetic<S, MAA, PAR>(a, rw, pl, g);
+  load_fluid<S, FAA, PAR, A>(a, rw, pl, f);
+  load_magnetic<S, MAA, PAR, A>(a, rw, pl, g);
   R F[3], Sb[3];
-  forcing_at(a, cell, F, Sb);
+  forcing_at<S, A>(a, cell, F, Sb);
   if (SAVE) save_state(a.save, a.n, cell, f, g);
   const FluidMoments<R> m = fluid_moments(f);
   const R inv_rho = R(1) / (R(1) + m.drho);
@@ -249,8 +284,8 @@ __global__ __launch_bounds__(kLocalThreads) void step_local(StepArgs<S> a) {
   current_from_moments(lam, Um, B, a.k.alpha, a.k.omega_b, J);
   if (SAVE) save_current(a.save, a.n, cell, J);
   collide_node<MODEL, sizeof(S) == 2>(f, g, m, U, Um, b, J, F, Sb, a.k);
-  store_fluid<S, FAA, PAR>(a, rw, pl, f);
-  store_magnetic<S, MAA, PAR>(a, rw, pl, g);
+  store_fluid<S, FAA, PAR, A>(a, rw, pl, f);
+  store_magnetic<S, MAA, PAR, A>(a, rw, pl, g);
 }
 
 // ------------------------------------------------------------------ stencil-route kernel
@@ -299,7 +334,7 @@ __global__ __launch_bounds__(kTX * Tile<typename Enc<S>::R>::ty, FLAME_ZMARCH_WA
   const uint32_t plane = static_cast<uint32_t>(nx) * ny;
   const Rows rw(active ? x : 0, active ? y : 0, nx, ny);
   auto half_src = [&](uint32_t cell, int c) -> R {
-    return a.force_b ? R(0.5) * ld(a.force_b + static_cast<size_t>(c) * a.n, cell) : R(0);
+    return a.force_b ? R(0.5) * ld<Addr::Global>(a.force_b + static_cast<size_t>(c) * a.n, cell) : R(0);
   };
   auto put_b = [&](int slot, const R (&g)[kM], uint32_t cell) {
 #pragma unroll
@@ -325,8 +360,10 @@ __global__ __launch_bounds__(kTX * Tile<typename Enc<S>::R>::ty, FLAME_ZMARCH_WA
 #pragma unroll
       for (int i = 0; i < 7; ++i) {
         const uint32_t off = rr.at(-xim(i, 0), -xim(i, 1)) + pl.at(-xim(i, 2));
-        const R v0 = E::dec(ld(a.g_src + static_cast<size_t>(i * 3 + c0) * a.stride, off), R(1.0 / E::mscale(i)));
-        const R v1 = E::dec(ld(a.g_src + static_cast<size_t>(i * 3 + c1) * a.stride, off), R(1.0 / E::mscale(i)));
+        const R v0 =
+            E::dec(ld<Addr::Global>(a.g_src + static_cast<size_t>(i * 3 + c0) * a.stride, off), R(1.0 / E::mscale(i)));
+        const R v1 =
+            E::dec(ld<Addr::Global>(a.g_src + static_cast<size_t>(i * 3 + c1) * a.stride, off), R(1.0 / E::mscale(i)));
         s0 = i == 0 ? v0 : s0 + v0;
         s1 = i == 0 ? v1 : s1 + v1;
       }
@@ -405,6 +442,19 @@ __global__ __launch_bounds__(kTX * Tile<typename Enc<S>::R>::ty, FLAME_ZMARCH_WA
   }
 }
 
+template <typename S, bool SAVE, int MODEL, Addr A>
+static void launch_local(const flame_ctx* c, const SetPtrs& s, const StepArgs<S>& a) {
+  const unsigned tx = row_threads(c);
+  const dim3 block(tx, 1, 1);
+  const dim3 grid(((c->p.nx + tx - 1) / tx) * c->p.ny * c->p.nz);
+  if (!s.fluid_aa)
+    hipLaunchKernelGGL((step_local<S, false, false, 0, SAVE, MODEL, A>), grid, block, 0, c->stream, a);
+  else if (c->parity == 0)
+    hipLaunchKernelGGL((step_local<S, true, true, 0, SAVE, MODEL, A>), grid, block, 0, c->stream, a);
+  else
+    hipLaunchKernelGGL((step_local<S, true, true, 1, SAVE, MODEL, A>), grid, block, 0, c->stream, a);
+}
+
 template <typename S, bool SAVE, int MODEL>
 static void launch_model(const flame_ctx* c, const SetPtrs& s, const StepArgs<S>& a) {
   using R = typename Enc<S>::R;
@@ -419,16 +469,10 @@ static void launch_model(const flame_ctx* c, const SetPtrs& s, const StepArgs<S>
       hipLaunchKernelGGL((step_zmarch<S, true, 0, SAVE, MODEL>), grid, block, 0, c->stream, a);
     else
       hipLaunchKernelGGL((step_zmarch<S, true, 1, SAVE, MODEL>), grid, block, 0, c->stream, a);
+  } else if (!c->global_addr && buffer_addressing_ok(c->p)) {
+    launch_local<S, SAVE, MODEL, Addr::Buffer>(c, s, a);
   } else {
-    const unsigned tx = row_threads(c);
-    const dim3 block(tx, 1, 1);
-    const dim3 grid(((c->p.nx + tx - 1) / tx) * c->p.ny * c->p.nz);
-    if (!s.fluid_aa)
-      hipLaunchKernelGGL((step_local<S, false, false, 0, SAVE, MODEL>), grid, block, 0, c->stream, a);
-    else if (par == 0)
-      hipLaunchKernelGGL((step_local<S, true, true, 0, SAVE, MODEL>), grid, block, 0, c->stream, a);
-    else
-      hipLaunchKernelGGL((step_local<S, true, true, 1, SAVE, MODEL>), grid, block, 0, c->stream, a);
+    launch_local<S, SAVE, MODEL, Addr::Global>(c, s, a);
   }
 }
 
