@@ -56,7 +56,7 @@ def kernel_fingerprint():
     import hashlib
     csrc = os.path.join(ROOT, "paper_2212_11024_amd", "csrc")
     data = b"".join(open(os.path.join(csrc, f), "rb").read()
-                    for f in ("flame_step.hip", "flame_device.h", "flame_internal.h"))
+                    for f in ("flame_step.hip", "flame_access.h", "flame_device.h", "flame_internal.h"))
     return hashlib.sha256(data).hexdigest()[:16]
 
 

@@ -275,7 +275,9 @@ flame_status flame_gather(flame_ctx* c, const int64_t* cells, int64_t n, double*
  * Arrays below are in the arithmetic type A (double for FLAME_F64, float otherwise), canonical
  * order, node stride n = nx*ny*nz: "state" [48 + 3][n] = pre-collision deviations (27 fluid,
  * 7 x 3 magnetic) followed by the J each node used; "lam" [48][n] = d loss / d(canonical
- * deviations) at one time. All are device pointers, caller-owned, asynchronous. */
+ * deviations) at one time. All are device pointers, caller-owned, asynchronous. The adjoint
+ * kernels address each [n] array with 32-bit byte offsets: flame_adjoint_step and
+ * flame_adjoint_trace_step return FLAME_E_INVAL when n values of A exceed 4 GiB. */
 
 /* One step, like flame_step(c, 1), that also writes the state it advanced from into state. */
 flame_status flame_step_save(flame_ctx* c, void* state);

@@ -11,6 +11,7 @@
 // state is pulled from the previous time level exactly as the forward step pulls it, and J is
 // recomputed from it, so the recompute is one ordinary step and writes nothing extra).
 
+#include "flame_access.h"
 #include "flame_internal.h"
 
 namespace flame {
@@ -53,52 +54,67 @@ __device__ __forceinline__ size_t anode(int x, int y, int z, int nx, int ny) {
   return (static_cast<size_t>(z) * ny + y) * nx + x;
 }
 
+// Addressing: 32-bit node offsets (Rows, Planes) from the uniform array bases, by 64-bit global
+// addresses. Buffer resources, which the forward step uses, raise these kernels' register count
+// to the 256 limit (one wave per SIMD) and slow the moment-route adjoint by 40%; the 32-bit
+// offsets alone took it from 0.257 to 0.245 ms per step at 128^3 FP32. The entry points refuse
+// arrays of more than 4 GiB.
+//
+// The adjoints of the next time level, gathered along the streaming: population q of node x went
+// to x + c_q, so its adjoint is lam_next[q] there.
+template <Addr A, typename R>
+__device__ __forceinline__ void gather_next(const R* lam_next, size_t n, const Rows& rw, const Planes& pl,
+                                            R (&mf)[kQ], R (&mg)[kM]) {
+#pragma unroll
+  for (int i = 0; i < kQ; ++i)
+    mf[i] = ld<A>(lam_next + static_cast<size_t>(i) * n, rw.at(cq(i, 0), cq(i, 1)) + pl.at(cq(i, 2)));
+#pragma unroll
+  for (int i = 0; i < 7; ++i) {
+    const uint32_t dn = rw.at(xim(i, 0), xim(i, 1)) + pl.at(xim(i, 2));
+#pragma unroll
+    for (int c = 0; c < 3; ++c) mg[i * 3 + c] = ld<A>(lam_next + static_cast<size_t>(kQ + i * 3 + c) * n, dn);
+  }
+}
+
 template <typename R, bool MOMENT>
 __global__ FLAME_ADJ_BOUNDS void adjoint_step_kernel(AdjArgs<R> a) {
+  constexpr Addr A = Addr::Global;
   unsigned bx, by, bz;
   logical_block((a.nx + blockDim.x - 1) / blockDim.x, a.ny, a.nz, bx, by, bz);
   const int x = bx * blockDim.x + threadIdx.x, y = by, z = bz;
   if (x >= a.nx) return;
-  const int nx = a.nx, ny = a.ny, nz = a.nz;
   const size_t n = a.n;
-  const size_t cell = anode(x, y, z, nx, ny);
+  const Rows rw(x, y, a.nx, a.ny);
+  const Planes pl(z, a.nz, static_cast<uint32_t>(a.nx) * a.ny);
+  const uint32_t cell = rw.at(0, 0) + pl.at(0);
   R F[3];
-  VjpState<R> st;
+  VjpState<R> fw;
   {
     R f[kQ], g[kM], J[3], S[3];
 #pragma unroll
-    for (int q = 0; q < kQ; ++q) f[q] = a.state[static_cast<size_t>(q) * n + cell];
+    for (int q = 0; q < kQ; ++q) f[q] = ld<A>(a.state + static_cast<size_t>(q) * n, cell);
 #pragma unroll
-    for (int q = 0; q < kM; ++q) g[q] = a.state[static_cast<size_t>(kQ + q) * n + cell];
+    for (int q = 0; q < kM; ++q) g[q] = ld<A>(a.state + static_cast<size_t>(kQ + q) * n, cell);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      J[c] = a.state[static_cast<size_t>(kQ + kM + c) * n + cell];
-      F[c] = a.force_u ? a.force_u[static_cast<size_t>(c) * n + cell] : R(0);
-      S[c] = a.force_b ? a.force_b[static_cast<size_t>(c) * n + cell] : R(0);
+      J[c] = ld<A>(a.state + static_cast<size_t>(kQ + kM + c) * n, cell);
+      F[c] = a.force_u ? ld<A>(a.force_u + static_cast<size_t>(c) * n, cell) : R(0);
+      S[c] = a.force_b ? ld<A>(a.force_b + static_cast<size_t>(c) * n, cell) : R(0);
     }
-    st = vjp_forward<R, MOMENT>(f, g, F, S, J, a.k);
+    fw = vjp_forward<R, MOMENT>(f, g, F, S, J, a.k);
   }
   adj_phase_fence();
   R mf[kQ], mg[kM];
-#pragma unroll
-  for (int i = 0; i < kQ; ++i)
-    mf[i] = a.lam_next[static_cast<size_t>(i) * n +
-                       anode(wrap(x + cq(i, 0), nx), wrap(y + cq(i, 1), ny), wrap(z + cq(i, 2), nz), nx, ny)];
-#pragma unroll
-  for (int i = 0; i < 7; ++i) {
-    const size_t dn = anode(wrap(x + xim(i, 0), nx), wrap(y + xim(i, 1), ny), wrap(z + xim(i, 2), nz), nx, ny);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) mg[i * 3 + c] = a.lam_next[static_cast<size_t>(kQ + i * 3 + c) * n + dn];
-  }
+  gather_next<A>(a.lam_next, n, rw, pl, mf, mg);
   R lf[kQ], lg[kM], lJ[3];
-  vjp_reverse<R, MOMENT>(st, F, a.k, mf, mg, lf, lg, lJ);
+  vjp_reverse<R, MOMENT>(fw, F, a.k, mf, mg, lf, lg, lJ);
 #pragma unroll
-  for (int q = 0; q < kQ; ++q) a.lam[static_cast<size_t>(q) * n + cell] = lf[q];
+  for (int q = 0; q < kQ; ++q) st<A>(a.lam + static_cast<size_t>(q) * n, cell, lf[q]);
 #pragma unroll
-  for (int q = 0; q < kM; ++q) a.lam[static_cast<size_t>(kQ + q) * n + cell] = lg[q];
+  for (int q = 0; q < kM; ++q) st<A>(a.lam + static_cast<size_t>(kQ + q) * n, cell, lg[q]);
   if (!MOMENT) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) a.lam_j[static_cast<size_t>(c) * n + cell] = lJ[c];
+    for (int c = 0; c < 3; ++c) st<A>(a.lam_j + static_cast<size_t>(c) * n, cell, lJ[c]);
   }
 }
 
@@ -118,59 +134,51 @@ struct AdjTraceArgs {
 
 template <typename S>
 __global__ FLAME_ADJ_BOUNDS void adjoint_trace_kernel(AdjTraceArgs<S> a) {
+  constexpr Addr A = Addr::Global;
   using E = Enc<S>;
   using R = typename E::R;
   unsigned bx, by, bz;
   logical_block((a.nx + blockDim.x - 1) / blockDim.x, a.ny, a.nz, bx, by, bz);
   const int x = bx * blockDim.x + threadIdx.x, y = by, z = bz;
   if (x >= a.nx) return;
-  const int nx = a.nx, ny = a.ny, nz = a.nz;
   const size_t n = a.n;
-  const size_t cell = anode(x, y, z, nx, ny);
+  const Rows rw(x, y, a.nx, a.ny);
+  const Planes pl(z, a.nz, static_cast<uint32_t>(a.nx) * a.ny);
+  const uint32_t cell = rw.at(0, 0) + pl.at(0);
   R F[3];
-  VjpState<R> st;
+  VjpState<R> fw;
   {
     // the step's pre-collision state pulled from the lattice, and the forward step's J recomputed
     // from it (moment route, same order of operations)
     R f[kQ], g[kM], Sb[3];
 #pragma unroll
     for (int i = 0; i < kQ; ++i)
-      f[i] = E::dec(a.src[static_cast<size_t>(i) * n +
-                          anode(wrap(x - cq(i, 0), nx), wrap(y - cq(i, 1), ny), wrap(z - cq(i, 2), nz), nx, ny)],
+      f[i] = E::dec(ld<A>(a.src + static_cast<size_t>(i) * n, rw.at(-cq(i, 0), -cq(i, 1)) + pl.at(-cq(i, 2))),
                     R(1.0 / E::fscale(i)));
 #pragma unroll
     for (int i = 0; i < 7; ++i) {
-      const size_t sn = anode(wrap(x - xim(i, 0), nx), wrap(y - xim(i, 1), ny), wrap(z - xim(i, 2), nz), nx, ny);
+      const uint32_t sn = rw.at(-xim(i, 0), -xim(i, 1)) + pl.at(-xim(i, 2));
 #pragma unroll
       for (int c = 0; c < 3; ++c)
-        g[i * 3 + c] = E::dec(a.src[static_cast<size_t>(kQ + i * 3 + c) * n + sn], R(1.0 / E::mscale(i)));
+        g[i * 3 + c] = E::dec(ld<A>(a.src + static_cast<size_t>(kQ + i * 3 + c) * n, sn), R(1.0 / E::mscale(i)));
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      F[c] = a.force_u ? a.force_u[static_cast<size_t>(c) * n + cell] : R(0);
-      Sb[c] = a.force_b ? a.force_b[static_cast<size_t>(c) * n + cell] : R(0);
+      F[c] = a.force_u ? ld<A>(a.force_u + static_cast<size_t>(c) * n, cell) : R(0);
+      Sb[c] = a.force_b ? ld<A>(a.force_b + static_cast<size_t>(c) * n, cell) : R(0);
     }
     const R unused[3] = {R(0), R(0), R(0)};
-    st = vjp_forward<R, true>(f, g, F, Sb, unused, a.k);
+    fw = vjp_forward<R, true>(f, g, F, Sb, unused, a.k);
   }
   adj_phase_fence();
   R mf[kQ], mg[kM];
-#pragma unroll
-  for (int i = 0; i < kQ; ++i)
-    mf[i] = a.lam_next[static_cast<size_t>(i) * n +
-                       anode(wrap(x + cq(i, 0), nx), wrap(y + cq(i, 1), ny), wrap(z + cq(i, 2), nz), nx, ny)];
-#pragma unroll
-  for (int i = 0; i < 7; ++i) {
-    const size_t dn = anode(wrap(x + xim(i, 0), nx), wrap(y + xim(i, 1), ny), wrap(z + xim(i, 2), nz), nx, ny);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) mg[i * 3 + c] = a.lam_next[static_cast<size_t>(kQ + i * 3 + c) * n + dn];
-  }
+  gather_next<A>(a.lam_next, n, rw, pl, mf, mg);
   R lf[kQ], lg[kM], lJ[3];
-  vjp_reverse<R, true>(st, F, a.k, mf, mg, lf, lg, lJ);
+  vjp_reverse<R, true>(fw, F, a.k, mf, mg, lf, lg, lJ);
 #pragma unroll
-  for (int q = 0; q < kQ; ++q) a.lam[static_cast<size_t>(q) * n + cell] = lf[q];
+  for (int q = 0; q < kQ; ++q) st<A>(a.lam + static_cast<size_t>(q) * n, cell, lf[q]);
 #pragma unroll
-  for (int q = 0; q < kM; ++q) a.lam[static_cast<size_t>(kQ + q) * n + cell] = lg[q];
+  for (int q = 0; q < kM; ++q) st<A>(a.lam + static_cast<size_t>(kQ + q) * n, cell, lg[q]);
 }
 
 // Stencil route: b_c of every magnetic population set feeds J of the six face neighbours; add
@@ -328,6 +336,14 @@ static hipError_t init_vjp_typed(const flame_ctx* c, const void* lam0, const dou
   return hipGetLastError();
 }
 
+// Every [n] array of the arithmetic type within 4 GiB (32-bit byte offsets in the kernels).
+static bool adjoint_arrays_fit(flame_ctx* c) {
+  const size_t bytes = c->n * (c->p.storage == FLAME_F64 ? 8 : 4);
+  if (bytes <= (size_t(1) << 32)) return true;
+  c->err = "reverse mode: each [n] array of the arithmetic type must fit in 4 GiB";
+  return false;
+}
+
 }  // namespace flame
 
 using namespace flame;
@@ -401,6 +417,7 @@ flame_status flame_adjoint_step(flame_ctx* c, const void* state, const void* lam
     c->err = "adjoint step needs state, lam_next and a distinct lam (and lam_j for the stencil route)";
     return FLAME_E_INVAL;
   }
+  if (!adjoint_arrays_fit(c)) return FLAME_E_INVAL;
   hipError_t e = c->p.storage == FLAME_F64 ? adjoint_typed<double>(c, state, lam_next, lam, lam_j)
                                            : adjoint_typed<float>(c, state, lam_next, lam, lam_j);
   if (e != hipSuccess) {
@@ -425,6 +442,7 @@ flame_status flame_adjoint_trace_step(flame_ctx* c, const void* src, const void*
     c->err = "trace adjoint needs src, lam_next and a distinct lam";
     return FLAME_E_INVAL;
   }
+  if (!adjoint_arrays_fit(c)) return FLAME_E_INVAL;
   hipError_t e;
   switch (c->p.storage) {
     case FLAME_F64: e = adjoint_trace_typed<double>(c, src, lam_next, lam); break;
