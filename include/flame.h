@@ -40,8 +40,8 @@
  *     (default 32), FLAME_ROW_THREADS = threads per row block of the node-local kernels, a
  *     multiple of 64 (default: the row rounded up to whole wavefronts, at most 256),
  *     FLAME_GLOBAL_ADDRESSING = 1 makes the node-local step of the paper's velocity sets address
- *     its arrays with 64-bit global addresses (default: buffer resources wherever every array
- *     ends at least 16 bytes below 4 GiB).
+ *     its arrays with 64-bit global addresses (default: buffer resources for FP16 and FP64
+ *     storage wherever every array ends at least 16 bytes below 4 GiB).
  */
 #ifndef FLAME_H
 #define FLAME_H
@@ -275,8 +275,8 @@ flame_status flame_gather(flame_ctx* c, const int64_t* cells, int64_t n, double*
  * Arrays below are in the arithmetic type A (double for FLAME_F64, float otherwise), canonical
  * order, node stride n = nx*ny*nz: "state" [48 + 3][n] = pre-collision deviations (27 fluid,
  * 7 x 3 magnetic) followed by the J each node used; "lam" [48][n] = d loss / d(canonical
- * deviations) at one time. All are device pointers, caller-owned, asynchronous. The adjoint
- * kernels address each [n] array with 32-bit byte offsets: flame_adjoint_step and
+ * deviations) at one time. All are device pointers, caller-owned, asynchronous. The kernels
+ * address each [n] array with 32-bit byte offsets: flame_step_save, flame_adjoint_step and
  * flame_adjoint_trace_step return FLAME_E_INVAL when n values of A exceed 4 GiB. */
 
 /* One step, like flame_step(c, 1), that also writes the state it advanced from into state. */

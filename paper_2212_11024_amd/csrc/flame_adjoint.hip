@@ -361,6 +361,7 @@ flame_status flame_step_save(flame_ctx* c, void* state) {
     c->err = "state is NULL";
     return FLAME_E_INVAL;
   }
+  if (!adjoint_arrays_fit(c)) return FLAME_E_INVAL;
   const SetPtrs ptr = set_ptrs(c);
   hipError_t e = launch_step(c, ptr, c->stride, state);
   if (e != hipSuccess) {

@@ -70,10 +70,10 @@ inline size_t population_stride(const flame_params& p) {
   const size_t align = 256 / vb;
   return (n + align - 1) / align * align + FLAME_STRIDE_PAD_BYTES / vb;
 }
-// The node-local step addresses its arrays through buffer resources (32-bit offsets, range
-// limit 2^32 - 1 bytes) when every population and forcing array ends at least 16 bytes below
-// 4 GiB, so that no access can meet the range limit whichever byte of it the hardware checks;
-// arrays of exactly 4 GiB (FP32 at 2^30 nodes) take the 64-bit global addresses instead.
+// The node-local step may address its arrays through buffer resources (32-bit offsets, range
+// limit 2^32 - 1 bytes) only when every population and forcing array ends at least 16 bytes
+// below 4 GiB, so that no access can meet the range limit whichever byte of it the hardware
+// checks; arrays of exactly 4 GiB take the 64-bit global addresses instead.
 inline bool buffer_addressing_ok(const flame_params& p) {
   const size_t limit = (size_t(1) << 32) - 16;
   const size_t n = static_cast<size_t>(p.nx) * p.ny * p.nz;

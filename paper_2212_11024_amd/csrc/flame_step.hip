@@ -13,8 +13,9 @@
 //
 // Two kernels:
 //   step_local  - moment-route J: every node independent, one node per thread, rows of up to
-//     256 nodes per block; arrays addressed through buffer resources when every array ends at
-//     least 16 bytes below 4 GiB, else through 64-bit global addresses (bitwise the same step).
+//     256 nodes per block; with FP16 and FP64 storage its arrays are addressed through buffer
+//     resources when every array ends at least 16 bytes below 4 GiB, otherwise (and with FP32
+//     storage) through 64-bit global addresses (bitwise the same step either way).
 //   step_zmarch - stencil J: a workgroup owns a 64 x 4 tile of (x, y) and marches along z. It
 //     keeps the field fluctuation b of three consecutive planes in LDS (computed once per node
 //     from that node's own magnetic populations, which it holds in registers for the next
@@ -159,18 +160,19 @@ __device__ __forceinline__ void collide_node(R (&f)[kQ], R (&g)[kM], const Fluid
   collide_magnetic(g, Um, B, b, J, Sb, k.alpha, k.omega_b);
 }
 
-// Record the node's pre-collision deviations (and the J it uses) for the adjoint.
-template <typename R>
+// Record the node's pre-collision deviations (and the J it uses) for the adjoint (streamed out
+// with the step's own addressing and store hint; read back only by the reverse sweep).
+template <Addr A, typename R>
 __device__ __forceinline__ void save_state(R* save, size_t n, uint32_t cell, const R (&f)[kQ], const R (&g)[kM]) {
 #pragma unroll
-  for (int q = 0; q < kQ; ++q) save[static_cast<size_t>(q) * n + cell] = f[q];
+  for (int q = 0; q < kQ; ++q) st<A>(save + static_cast<size_t>(q) * n, cell, f[q]);
 #pragma unroll
-  for (int q = 0; q < kM; ++q) save[static_cast<size_t>(kQ + q) * n + cell] = g[q];
+  for (int q = 0; q < kM; ++q) st<A>(save + static_cast<size_t>(kQ + q) * n, cell, g[q]);
 }
-template <typename R>
+template <Addr A, typename R>
 __device__ __forceinline__ void save_current(R* save, size_t n, uint32_t cell, const R (&J)[3]) {
 #pragma unroll
-  for (int c = 0; c < 3; ++c) save[static_cast<size_t>(kQ + kM + c) * n + cell] = J[c];
+  for (int c = 0; c < 3; ++c) st<A>(save + static_cast<size_t>(kQ + kM + c) * n, cell, J[c]);
 }
 
 // ------------------------------------------------------------------ moment-route kernel
@@ -193,7 +195,7 @@ __global__ __launch_bounds__(kLocalThreads) void step_local(StepArgs<S> a) {
   load_magnetic<S, MAA, PAR, A>(a, rw, pl, g);
   R F[3], Sb[3];
   forcing_at<S, A>(a, cell, F, Sb);
-  if (SAVE) save_state(a.save, a.n, cell, f, g);
+  if (SAVE) save_state<A>(a.save, a.n, cell, f, g);
   const FluidMoments<R> m = fluid_moments(f);
   const R inv_rho = R(1) / (R(1) + m.drho);
   const R U[3] = {(m.jx + R(0.5) * F[0]) * inv_rho, (m.jy + R(0.5) * F[1]) * inv_rho,
@@ -207,7 +209,7 @@ __global__ __launch_bounds__(kLocalThreads) void step_local(StepArgs<S> a) {
   const R(&Um)[3] = (MODEL & kModelEMHD) != 0 ? zero.v : U;
   R J[3];
   current_from_moments(lam, Um, B, a.k.alpha, a.k.omega_b, J);
-  if (SAVE) save_current(a.save, a.n, cell, J);
+  if (SAVE) save_current<A>(a.save, a.n, cell, J);
   collide_node<MODEL, sizeof(S) == 2>(f, g, m, U, Um, b, J, F, Sb, a.k);
   store_fluid<S, FAA, PAR, A>(a, rw, pl, f);
   store_magnetic<S, MAA, PAR, A>(a, rw, pl, g);
@@ -331,7 +333,7 @@ __global__ __launch_bounds__(kTX * Tile<typename Enc<S>::R>::ty, FLAME_ZMARCH_WA
       R f[kQ];
       load_fluid<S, FAA, PAR>(a, rw, pl, f);
       forcing_at(a, cell, F, Sb);
-      if (SAVE) save_state(a.save, a.n, cell, f, g);
+      if (SAVE) save_state<Addr::Global>(a.save, a.n, cell, f, g);
       const FluidMoments<R> m = fluid_moments(f);
       const R inv_rho = R(1) / (R(1) + m.drho);
       U[0] = (m.jx + R(0.5) * F[0]) * inv_rho;
@@ -354,7 +356,7 @@ __global__ __launch_bounds__(kTX * Tile<typename Enc<S>::R>::ty, FLAME_ZMARCH_WA
       J[1] = R(0.5) * (N[py][px][0] - P[py][px][0]) - R(0.5) * (C[py][px + 1][2] - C[py][px - 1][2]);
       J[2] = R(0.5) * (C[py][px + 1][1] - C[py][px - 1][1]) - R(0.5) * (C[py + 1][px][0] - C[py - 1][px][0]);
       const R B[3] = {a.k.b0[0] + b[0], a.k.b0[1] + b[1], a.k.b0[2] + b[2]};
-      if (SAVE) save_current(a.save, a.n, cell, J);
+      if (SAVE) save_current<Addr::Global>(a.save, a.n, cell, J);
       const Zero3<R> zero;
       collide_magnetic(g, (MODEL & kModelEMHD) != 0 ? zero.v : U, B, b, J, Sb, a.k.alpha, a.k.omega_b);
       store_magnetic<S, false, 0>(a, rw, pl, g);
@@ -394,9 +396,16 @@ static void launch_model(const flame_ctx* c, const SetPtrs& s, const StepArgs<S>
       hipLaunchKernelGGL((step_zmarch<S, true, 0, SAVE, MODEL>), grid, block, 0, c->stream, a);
     else
       hipLaunchKernelGGL((step_zmarch<S, true, 1, SAVE, MODEL>), grid, block, 0, c->stream, a);
-  } else if (!c->global_addr && buffer_addressing_ok(c->p)) {
-    launch_local<S, SAVE, MODEL, Addr::Buffer>(c, s, a);
   } else {
+    // FP16 and FP64 storage: buffer resources (timed on the same buffers at 512^3, FP16 6.05-6.12
+    // against 6.43-6.50 ms, FP64 18.91-19.13 against 19.17-19.30 ms); FP32 keeps the global
+    // addresses, with which it runs 1.1-2.5% faster (9.09 against 9.20 ms on a fast placement)
+    if constexpr (sizeof(S) != 4) {
+      if (!c->global_addr && buffer_addressing_ok(c->p)) {
+        launch_local<S, SAVE, MODEL, Addr::Buffer>(c, s, a);
+        return;
+      }
+    }
     launch_local<S, SAVE, MODEL, Addr::Global>(c, s, a);
   }
 }
