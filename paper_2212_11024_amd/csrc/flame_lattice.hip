@@ -35,10 +35,14 @@ __device__ __forceinline__ void vxyz(size_t cell, int nx, int ny, int& x, int& y
 struct SetGeom {
   int nx, ny, nz;
   size_t stride;
+  // the slot and the node of that population
+  __device__ int slot(int mode, int i, int opp) const { return mode == 1 ? opp : i; }
+  __device__ size_t node(int mode, int vx, int vy, int vz, int x, int y, int z) const {
+    if (mode == 0) return vnode(x, y, z, nx, ny);
+    return vnode(wrap(x - vx, nx), wrap(y - vy, ny), wrap(z - vz, nz), nx, ny);
+  }
   __device__ size_t at(int mode, int i, int opp, int vx, int vy, int vz, int x, int y, int z) const {
-    if (mode == 0) return static_cast<size_t>(i) * stride + vnode(x, y, z, nx, ny);
-    const size_t dn = vnode(wrap(x - vx, nx), wrap(y - vy, ny), wrap(z - vz, nz), nx, ny);
-    return static_cast<size_t>(mode == 1 ? opp : i) * stride + dn;
+    return static_cast<size_t>(slot(mode, i, opp)) * stride + node(mode, vx, vy, vz, x, y, z);
   }
 };
 
@@ -78,8 +82,8 @@ __global__ __launch_bounds__(256) void variant_step(VStepArgs<S> a) {
                   R(1.0 / fscale<S, FL>(i)));
 #pragma unroll
   for (int i = 0; i < ML::m; ++i) {
-    const size_t base = geo.at(rmode, i, ML::opp(i), ML::xi(i, 0), ML::xi(i, 1), ML::xi(i, 2), x, y, z);
-    const size_t slot = base / a.stride, node = base % a.stride;
+    const size_t slot = geo.slot(rmode, i, ML::opp(i));
+    const size_t node = geo.node(rmode, ML::xi(i, 0), ML::xi(i, 1), ML::xi(i, 2), x, y, z);
 #pragma unroll
     for (int c = 0; c < 3; ++c)
       g[i * 3 + c] = E::dec(a.g_src[(slot * 3 + c) * a.stride + node], R(1.0 / fscale<S, ML>(i)));
@@ -126,8 +130,8 @@ struct VView {
            fscale<S, FL>(i);
   }
   __device__ double g(int i, int c, int x, int y, int z) const {
-    const size_t base = geo.at(gmode, i, ML::opp(i), ML::xi(i, 0), ML::xi(i, 1), ML::xi(i, 2), x, y, z);
-    const size_t slot = base / geo.stride, node = base % geo.stride;
+    const size_t slot = geo.slot(gmode, i, ML::opp(i));
+    const size_t node = geo.node(gmode, ML::xi(i, 0), ML::xi(i, 1), ML::xi(i, 2), x, y, z);
     return static_cast<double>(G[(slot * 3 + c) * geo.stride + node]) / fscale<S, ML>(i);
   }
 };
