@@ -117,3 +117,40 @@ def extended_error(solver, ref):
     num = ((df - xf) ** 2).sum() + ((dg - xg) ** 2).sum()
     den = (xf ** 2).sum() + (xg ** 2).sum()
     return float(np.sqrt(num / den))
+
+
+def neighbourhood(centres, n):
+    """Linear indices of the periodic 5^3 boxes around (x, y, z) centres on an n^3 grid."""
+    off = np.arange(-2, 3)
+    zz, yy, xx = np.meshgrid(off, off, off, indexing="ij")
+    out = []
+    for x, y, z in centres:
+        out.append(((((z + zz) % n) * n + (y + yy) % n) * n + (x + xx) % n).reshape(-1))
+    return np.concatenate(out)
+
+
+def sampled_step_error(solver, centres, n, nu, eta, d_i, b0, jmode="moment"):
+    """One unforced step of the GPU run checked on sampled nodes: the pre-step populations of each
+    centre's periodic 5^3 neighbourhood are read back, the oracle steps that box once (the centre
+    depends only on nodes within two cells), and the centre's post-step populations are compared.
+    Returns (relative L2 error over the centres, worst single centre)."""
+    nb = torch.as_tensor(neighbourhood(centres, n), device=solver.device)
+    mid = torch.as_tensor([((z * n + y) * n + x) for x, y, z in centres], device=solver.device)
+    k = len(centres)
+    p = scheme.Params(5, 5, 5, nu, eta, d_i, b0, jmode, "closed")
+    rest = scheme.rest_state(p)
+    pre = solver.gather(nb).cpu().view(k, 125, 48)
+    solver.step(1)
+    post = solver.gather(mid, deviations=True).cpu()
+    num = den = worst = 0.0
+    for i in range(k):
+        f = pre[i, :, :27].T.reshape(27, 5, 5, 5).contiguous()
+        g = pre[i, :, 27:].T.reshape(7, 3, 5, 5, 5).contiguous()
+        st = scheme.step(scheme.State(f, g), p, 1)
+        want = torch.cat([(st.f - rest.f)[:, 2, 2, 2], (st.g - rest.g)[:, :, 2, 2, 2].reshape(-1)])
+        d = float(((post[i] - want) ** 2).sum())
+        w = float((want ** 2).sum())
+        num += d
+        den += w
+        worst = max(worst, (d / w) ** 0.5)
+    return (num / den) ** 0.5, worst

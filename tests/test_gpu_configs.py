@@ -19,6 +19,7 @@ import pytest
 import torch
 
 import synthetic
+from parity_helpers import sampled_step_error
 
 pytestmark = pytest.mark.gpu
 
@@ -170,6 +171,13 @@ def _free_hbm_gb():
     return free / 1e9
 
 
+# sampled centres of the 1024^3 run: both ends of the grid and of a row, the wraps, random nodes
+LARGE_CENTRES = [(1023, 1023, 1023), (0, 0, 0), (1022, 1023, 1023), (1023, 0, 511), (255, 256, 1023),
+                 (256, 511, 0), (511, 767, 768), (17, 900, 333), (640, 1, 1022), (1000, 64, 96)]
+# the full-size sampled bars (tests/test_gpu_fullsize.py): one step from a state read back exactly
+LARGE_BARS = {"f32": (1e-5, 1e-4), "f16": (1e-3, 3e-3)}
+
+
 def test_large_fp16_1024():
     """The large configuration: 1024^3, FP16 deviation storage with FP32 arithmetic, moment J,
     AA in place (103 GB of populations), decaying turbulence from seeded shells 1..4 (rms 0.02),
@@ -178,7 +186,9 @@ def test_large_fp16_1024():
     reference. The state starts at equilibrium (the non-equilibrium parts need the velocity and
     field gradients, 77 GB each, which do not fit beside the FP32 populations). Reported:
     throughput of both, the first record with non-finite values (none expected: the moment
-    route is stable beyond the whistler CFL bound), FP16 against FP32 shell spectra. Bar on the
+    route is stable beyond the whistler CFL bound), FP16 against FP32 shell spectra, and after
+    the 500 steps one even and one odd step of each run against the oracle on sampled nodes,
+    among them the grid's last node, whose values end the 4 GiB FP32 arrays. Bar on the
     energetic shells 1..4: FP16 rounds each stored deviation to ~4.9e-4 relative per step, a
     random walk of ~1.1e-2 over 500 steps; measured 3.7e-4 at most (1024^3: FP16 51.5 ms/step,
     FP32 68.7 ms/step). Skipped only when the device has less free memory than the FP32 run
@@ -215,6 +225,14 @@ def test_large_fp16_1024():
             print(f"[large] {storage} step {(k + 1) * every}: E_kin {float(red[0]):.6e} E_mag {float(red[1]):.6e} "
                   f"non-finite {int(red[8])}", flush=True)
         spec = {f: s.spectrum(f, nsh) for f in ("u", "B")}
+        # one even and one odd step checked against the oracle on sampled nodes, among them the
+        # last node of the grid, whose values sit at the very end of the 4 GiB (FP32) and 2 GiB
+        # (FP16) population arrays
+        for _ in range(2):
+            err, worst = sampled_step_error(s, LARGE_CENTRES, n, 5e-4, 5e-4, 32.0, (0.0, 0.0, 0.0))
+            print(f"[large] {storage} sampled one-step parity after {s.steps} steps: {err:.3e}, worst node "
+                  f"{worst:.3e}", flush=True)
+            assert err < LARGE_BARS[storage][0] and worst < LARGE_BARS[storage][1]
         s.close()
         del s
         torch.cuda.empty_cache()
