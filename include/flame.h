@@ -38,7 +38,8 @@
  *   - Launch-shape tuning, read from the environment by flame_init (results do not depend on
  *     it, bitwise): FLAME_ZCHUNK_PLANES = planes per workgroup of the curl-stencil kernel
  *     (default 32), FLAME_ROW_THREADS = threads per row block of the node-local kernels, a
- *     multiple of 64 (default: the row rounded up to whole wavefronts, at most 256),
+ *     multiple of 64 up to 256, larger values taken as 256 (default: the row rounded up to
+ *     whole wavefronts, at most 256),
  *     FLAME_GLOBAL_ADDRESSING = 1 makes the node-local step of the paper's velocity sets address
  *     its arrays with 64-bit global addresses (default: buffer resources for FP16 and FP64
  *     storage wherever every array ends at least 16 bytes below 4 GiB).

@@ -941,7 +941,7 @@ flame_status flame_init(const flame_params* p, const double* u, const double* b,
   c->omega_b = 1.0 / (4.0 * p->eta + 0.5);
   // launch-shape tuning (multiples of 64 threads per row block; any positive plane count)
   if (const char* v = getenv("FLAME_ZCHUNK_PLANES")) c->zchunk = std::max(0, atoi(v));
-  if (const char* v = getenv("FLAME_ROW_THREADS")) c->row_tx = std::max(0, atoi(v)) / 64 * 64;
+  if (const char* v = getenv("FLAME_ROW_THREADS")) c->row_tx = std::min(std::max(0, atoi(v)) / 64 * 64, kRowThreadsMax);
   if (const char* v = getenv("FLAME_GLOBAL_ADDRESSING")) c->global_addr = atoi(v) != 0;
   const double* B0 = p->b0;
   flame_rest_populations(p, c->frest, nullptr);   // q <= 27 values

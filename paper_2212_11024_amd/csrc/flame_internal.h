@@ -127,9 +127,13 @@ __device__ __forceinline__ void logical_block(unsigned gx, unsigned gy, unsigned
 // Threads of a row block of the node-local kernels: one row of nx nodes rounded up to whole
 // wavefronts, at most 256 (longer rows take several blocks), so that short rows leave no wave
 // of a block idle.
-inline unsigned row_threads(int nx) { return static_cast<unsigned>(std::min(256, (nx + 63) / 64 * 64)); }
+// Threads per row block of the node-local kernels, whose launch bounds are 256 threads: never more
+// than that, whatever FLAME_ROW_THREADS asks for.
+constexpr int kRowThreadsMax = 256;
+inline unsigned row_threads(int nx) { return static_cast<unsigned>(std::min(kRowThreadsMax, (nx + 63) / 64 * 64)); }
 inline unsigned row_threads(const flame_ctx* c) {
-  return c->row_tx > 0 ? static_cast<unsigned>(std::min(c->row_tx, (c->p.nx + 63) / 64 * 64)) : row_threads(c->p.nx);
+  return c->row_tx > 0 ? static_cast<unsigned>(std::min({c->row_tx, kRowThreadsMax, (c->p.nx + 63) / 64 * 64}))
+                       : row_threads(c->p.nx);
 }
 
 // One fused step over the sets s, whose population arrays are stride elements apart; with

@@ -177,6 +177,7 @@ __device__ __forceinline__ void save_current(R* save, size_t n, uint32_t cell, c
 
 // ------------------------------------------------------------------ moment-route kernel
 constexpr int kLocalThreads = 256;
+static_assert(kLocalThreads == kRowThreadsMax, "row blocks are launched with up to kRowThreadsMax threads");
 
 template <typename S, bool FAA, bool MAA, int PAR, bool SAVE, int MODEL, Addr A>
 __global__ __launch_bounds__(kLocalThreads) void step_local(StepArgs<S> a) {

@@ -125,11 +125,12 @@ def test_launch_shape_independence(storage, monkeypatch):
     curl-stencil kernel (FLAME_ZCHUNK_PLANES: the built-in 32, 5 with a ragged last chunk, 1, the
     whole column and more than it) and the threads per row block of the node-local kernels
     (FLAME_ROW_THREADS: one block per row, or 64, 128 and 192 threads, so that a 257-node row
-    spans several blocks with a ragged last one), and the addressing of the node-local step
+    spans several blocks with a ragged last one; 512 is taken as the kernels' launch bound of
+    256), and the addressing of the node-local step
     (FLAME_GLOBAL_ADDRESSING: buffer resources or 64-bit global addresses), on forced runs over 7
     steps (both AA parities)."""
     cases = [(Case(13, 10, 37, jmode="stencil", forced=True, seed=61), "FLAME_ZCHUNK_PLANES", ["0", "5", "1", "37", "64"]),
-             (Case(257, 3, 4, jmode="moment", forced=True, seed=63), "FLAME_ROW_THREADS", ["0", "64", "128", "192"]),
+             (Case(257, 3, 4, jmode="moment", forced=True, seed=63), "FLAME_ROW_THREADS", ["0", "64", "128", "192", "512"]),
              (Case(33, 17, 9, jmode="moment", forced=True, seed=65), "FLAME_GLOBAL_ADDRESSING", ["0", "1"])]
     for case, var, values in cases:
         ref = None
