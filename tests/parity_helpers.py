@@ -129,23 +129,33 @@ def neighbourhood(centres, n):
     return np.concatenate(out)
 
 
-def sampled_step_error(solver, centres, n, nu, eta, d_i, b0, jmode="moment"):
-    """One unforced step of the GPU run checked on sampled nodes: the pre-step populations of each
-    centre's periodic 5^3 neighbourhood are read back, the oracle steps that box once (the centre
-    depends only on nodes within two cells), and the centre's post-step populations are compared.
+def sampled_step_error(solver, centres, n, nu, eta, d_i, b0, jmode="moment", force=None, collision="central",
+                       magnetic="hall", fluid_lattice="d3q27", magnetic_lattice="d3q7"):
+    """One step of the GPU run checked on sampled nodes: the pre-step populations of each centre's
+    periodic 5^3 neighbourhood are read back, the oracle steps that box once (the centre depends
+    only on nodes within two cells), and the centre's post-step populations are compared. force:
+    the (fu, fb) fields as the kernel sees them (float64 tensors (3, n, n, n)), or None.
     Returns (relative L2 error over the centres, worst single centre)."""
-    nb = torch.as_tensor(neighbourhood(centres, n), device=solver.device)
+    nb_np = neighbourhood(centres, n)
+    nb = torch.as_tensor(nb_np, device=solver.device)
     mid = torch.as_tensor([((z * n + y) * n + x) for x, y, z in centres], device=solver.device)
-    k = len(centres)
-    p = scheme.Params(5, 5, 5, nu, eta, d_i, b0, jmode, "closed")
-    rest = scheme.rest_state(p)
-    pre = solver.gather(nb).cpu().view(k, 125, 48)
+    k, q, m = len(centres), solver.q, solver.m
+    kw = dict(collision=collision, magnetic=magnetic, fluid_lattice=fluid_lattice, magnetic_lattice=magnetic_lattice)
+    rest = scheme.rest_state(scheme.Params(5, 5, 5, nu, eta, d_i, b0, jmode, "closed", **kw))
+    pre = solver.gather(nb).cpu().view(k, 125, q + 3 * m)
+    fpre = bpre = None
+    if force is not None:
+        fpre = force[0].flatten(1)[:, nb].cpu().view(3, k, 125)
+        bpre = force[1].flatten(1)[:, nb].cpu().view(3, k, 125)
     solver.step(1)
     post = solver.gather(mid, deviations=True).cpu()
     num = den = worst = 0.0
     for i in range(k):
-        f = pre[i, :, :27].T.reshape(27, 5, 5, 5).contiguous()
-        g = pre[i, :, 27:].T.reshape(7, 3, 5, 5, 5).contiguous()
+        f = pre[i, :, :q].T.reshape(q, 5, 5, 5).contiguous()
+        g = pre[i, :, q:].T.reshape(m, 3, 5, 5, 5).contiguous()
+        fu = None if fpre is None else fpre[:, i].reshape(3, 5, 5, 5)
+        fb = None if bpre is None else bpre[:, i].reshape(3, 5, 5, 5)
+        p = scheme.Params(5, 5, 5, nu, eta, d_i, b0, jmode, "closed", fu, fb, **kw)
         st = scheme.step(scheme.State(f, g), p, 1)
         want = torch.cat([(st.f - rest.f)[:, 2, 2, 2], (st.g - rest.g)[:, :, 2, 2, 2].reshape(-1)])
         d = float(((post[i] - want) ** 2).sum())

@@ -14,7 +14,7 @@ import torch
 import synthetic
 from oracle import analytic, diagnostics, scheme
 
-from parity_helpers import Case, deviation_error, gpu_solver, oracle_run
+from parity_helpers import Case, deviation_error, gpu_solver, oracle_run, sampled_step_error
 
 pytestmark = pytest.mark.gpu
 
@@ -31,6 +31,36 @@ CASES = {
 
 def _print(name, **kw):
     print(f"[lattice] {name} {kw}", flush=True)
+
+
+# sampled centres at 512^3: the edges of the 256-node row blocks, the periodic wraps, random nodes
+FULL_CENTRES = [(255, 124, 63), (256, 127, 64), (0, 0, 0), (511, 511, 511), (511, 256, 1), (63, 3, 31),
+                (64, 4, 32), (448, 507, 447), (17, 300, 200), (401, 12, 499), (128, 384, 256), (333, 77, 5)]
+
+
+@pytest.mark.parametrize("fl,ml,collision", [("d3q19", "d3q7", "bgk"), ("d3q27", "d3q15", "central"),
+                                             ("d3q27", "d3q27", "central")])
+def test_variant_sampled_parity_at_benchmark_size(fl, ml, collision):
+    """The variant legs of the benchmark (512^3 forced Hall-MHD turbulence, FP32 deviation storage,
+    AA layout, moment J) checked against the oracle on sampled nodes after an odd and an even
+    number of steps, with the full-size FP32 bars of the paper's sets."""
+    import bench
+    n = 512
+    _print("benchmark size", fl=fl, ml=ml, collision=collision)
+    fields = bench.workload_fields(n, "cuda")
+    s = bench.make_solver(n, "f32", "moment", "aa", fields=fields, collision=collision, fluid_lattice=fl,
+                          magnetic_lattice=ml)
+    force = (fields[4].float().double(), fields[5].float().double())
+    del fields
+    for advance in (3, 1):
+        s.step(advance)
+        err, worst = sampled_step_error(s, FULL_CENTRES, n, bench.PHYS["nu"], bench.PHYS["eta"], bench.PHYS["d_i"],
+                                        bench.PHYS["b0"], force=force, collision=collision, fluid_lattice=fl,
+                                        magnetic_lattice=ml)
+        print(f"[lattice] {fl}/{ml} 512^3 f32 after {s.steps} steps: sampled relative error {err:.3e}, "
+              f"worst node {worst:.3e}", flush=True)
+        assert err < 1e-5 and worst < 1e-4
+    s.close()
 
 
 @pytest.mark.parametrize("branch", [+1, -1])
