@@ -38,26 +38,30 @@ FULL_CENTRES = [(255, 124, 63), (256, 127, 64), (0, 0, 0), (511, 511, 511), (511
                 (64, 4, 32), (448, 507, 447), (17, 300, 200), (401, 12, 499), (128, 384, 256), (333, 77, 5)]
 
 
-@pytest.mark.parametrize("fl,ml,collision", [("d3q19", "d3q7", "bgk"), ("d3q27", "d3q15", "central"),
-                                             ("d3q27", "d3q27", "central")])
-def test_variant_sampled_parity_at_benchmark_size(fl, ml, collision):
+@pytest.mark.parametrize("fl,ml,collision,magnetic", [("d3q19", "d3q7", "bgk", "hall"),
+                                                      ("d3q27", "d3q15", "central", "hall"),
+                                                      ("d3q27", "d3q27", "central", "hall"),
+                                                      ("d3q27", "d3q7", "bgk", "hall"),
+                                                      ("d3q27", "d3q7", "central", "emhd")])
+def test_variant_sampled_parity_at_benchmark_size(fl, ml, collision, magnetic):
     """The variant legs of the benchmark (512^3 forced Hall-MHD turbulence, FP32 deviation storage,
-    AA layout, moment J) checked against the oracle on sampled nodes after an odd and an even
-    number of steps, with the full-size FP32 bars of the paper's sets."""
+    AA layout, moment J): the velocity-set variants and, on the paper's sets, the BGK fluid
+    collision and electron MHD, checked against the oracle on sampled nodes after an odd and an
+    even number of steps, with the full-size FP32 bars of the paper's model."""
     import bench
     n = 512
-    _print("benchmark size", fl=fl, ml=ml, collision=collision)
+    _print("benchmark size", fl=fl, ml=ml, collision=collision, magnetic=magnetic)
     fields = bench.workload_fields(n, "cuda")
-    s = bench.make_solver(n, "f32", "moment", "aa", fields=fields, collision=collision, fluid_lattice=fl,
-                          magnetic_lattice=ml)
+    s = bench.make_solver(n, "f32", "moment", "aa", fields=fields, collision=collision, magnetic=magnetic,
+                          fluid_lattice=fl, magnetic_lattice=ml)
     force = (fields[4].float().double(), fields[5].float().double())
     del fields
     for advance in (3, 1):
         s.step(advance)
         err, worst = sampled_step_error(s, FULL_CENTRES, n, bench.PHYS["nu"], bench.PHYS["eta"], bench.PHYS["d_i"],
-                                        bench.PHYS["b0"], force=force, collision=collision, fluid_lattice=fl,
-                                        magnetic_lattice=ml)
-        print(f"[lattice] {fl}/{ml} 512^3 f32 after {s.steps} steps: sampled relative error {err:.3e}, "
+                                        bench.PHYS["b0"], force=force, collision=collision, magnetic=magnetic,
+                                        fluid_lattice=fl, magnetic_lattice=ml)
+        print(f"[lattice] {fl}/{ml} {collision}/{magnetic} 512^3 f32 after {s.steps} steps: sampled relative error {err:.3e}, "
               f"worst node {worst:.3e}", flush=True)
         assert err < 1e-5 and worst < 1e-4
     s.close()
