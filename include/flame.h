@@ -12,8 +12,9 @@
  *     moments (eq. soe_current_density) or from the central-difference curl of B;
  *   - streaming of both sets along their lattice velocities.
  * Relaxation rates follow the paper: 1/omega = 3 nu + 1/2, 1/omega_B = 4 eta + 1/2.
- * Variants selected in flame_params: the BGK fluid collision (S = omega I) and the
- * electron-MHD magnetic equilibrium (Sec. 6). Diagnostics: FP64 reductions, shell energy and
+ * Variants selected in flame_params: the BGK fluid collision (S = omega I), the
+ * electron-MHD magnetic equilibrium (Sec. 6) and the other velocity sets of the lattice figure of
+ * Sec. 3.1 (D3Q19 fluid, D3Q15 / D3Q27 magnetic). Diagnostics: FP64 reductions, shell energy and
  * dissipation spectra, and the energy transfer terms of the scale-by-scale budget (Sec. 4.4).
  *
  * Conventions shared by every entry point
