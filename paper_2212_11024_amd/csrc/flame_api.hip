@@ -409,7 +409,7 @@ __global__ __launch_bounds__(kRedThreads) void reduce_kernel(AuxArgs<S> a, doubl
   __shared__ double sh[FLAME_NRED][kRedThreads];
   for (int k = 0; k < FLAME_NRED; ++k) sh[k][threadIdx.x] = acc[k];
   __syncthreads();
-  for (int s = kRedThreads / 2; s > 0; s >>= 1) {
+  for (unsigned s = kRedThreads / 2; s > 0; s >>= 1) {
     if (threadIdx.x < s) {
       for (int k = 0; k < FLAME_NRED; ++k) {
         const double o = sh[k][threadIdx.x + s];
@@ -803,7 +803,7 @@ __global__ void max_field_kernel(const double* b, double b0x, double b0y, double
   }
   sh[threadIdx.x] = m;
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
+  for (unsigned s = 128; s > 0; s >>= 1) {
     if (threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
     __syncthreads();
   }

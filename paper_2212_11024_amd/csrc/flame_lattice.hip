@@ -453,7 +453,7 @@ __global__ __launch_bounds__(kVRedThreads) void variant_reduce(VAux<S, FL, ML> a
   __shared__ double sh[FLAME_NRED][kVRedThreads];
   for (int k = 0; k < FLAME_NRED; ++k) sh[k][threadIdx.x] = acc[k];
   __syncthreads();
-  for (int s = kVRedThreads / 2; s > 0; s >>= 1) {
+  for (unsigned s = kVRedThreads / 2; s > 0; s >>= 1) {
     if (threadIdx.x < s)
       for (int k = 0; k < FLAME_NRED; ++k) {
         const double o = sh[k][threadIdx.x + s];
