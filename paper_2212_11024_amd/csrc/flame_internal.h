@@ -71,14 +71,16 @@ inline size_t population_stride(const flame_params& p) {
   return (n + align - 1) / align * align + FLAME_STRIDE_PAD_BYTES / vb;
 }
 // The node-local step may address its arrays through buffer resources (32-bit offsets, range
-// limit 2^32 - 1 bytes) only when every population and forcing array ends at least 16 bytes
-// below 4 GiB, so that no access can meet the range limit whichever byte of it the hardware
-// checks; arrays of exactly 4 GiB take the 64-bit global addresses instead.
-inline bool buffer_addressing_ok(const flame_params& p) {
+// limit 2^32 - 1 bytes) only when every array it touches ends at least 16 bytes below 4 GiB, so
+// that no access can meet the range limit whichever byte of it the hardware checks: the
+// population arrays, and, when the launch reads forcing or writes a saved state
+// (arith_arrays), the [n] arrays of the arithmetic type. Larger arrays take the 64-bit global
+// addresses instead.
+inline bool buffer_addressing_ok(const flame_params& p, bool arith_arrays) {
   const size_t limit = (size_t(1) << 32) - 16;
   const size_t n = static_cast<size_t>(p.nx) * p.ny * p.nz;
   const size_t arith = p.storage == FLAME_F64 ? 8 : 4;
-  return population_stride(p) * value_bytes(p.storage) <= limit && n * arith <= limit;
+  return population_stride(p) * value_bytes(p.storage) <= limit && (!arith_arrays || n * arith <= limit);
 }
 // Model bits of the step kernels: 1 = BGK fluid collision, 2 = electron MHD; 0 is the paper's.
 inline int step_model(const flame_params& p) {

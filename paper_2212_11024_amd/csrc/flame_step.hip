@@ -402,7 +402,8 @@ static void launch_model(const flame_ctx* c, const SetPtrs& s, const StepArgs<S>
     // against 6.43-6.50 ms, FP64 18.91-19.13 against 19.17-19.30 ms); FP32 keeps the global
     // addresses, with which it runs 1.1-2.5% faster (9.09 against 9.20 ms on a fast placement)
     if constexpr (sizeof(S) != 4) {
-      if (!c->global_addr && buffer_addressing_ok(c->p)) {
+      const bool arith_arrays = SAVE || c->p.force_u || c->p.force_b;
+      if (!c->global_addr && buffer_addressing_ok(c->p, arith_arrays)) {
         launch_local<S, SAVE, MODEL, Addr::Buffer>(c, s, a);
         return;
       }

@@ -1,6 +1,7 @@
 // Host build of the library's per-node arithmetic (test infrastructure): lets the CPU test
 // suite check the kernels' collision and its reverse pass against the oracle without a GPU.
 #include "../../paper_2212_11024_amd/csrc/flame_device.h"
+#include "../../paper_2212_11024_amd/csrc/flame_internal.h"
 #include "../../paper_2212_11024_amd/csrc/flame_lattice.h"
 
 using namespace flame;
@@ -137,6 +138,25 @@ int hc_variant_collide(int fq, int mq, int bgk, int emhd, const double* f_in, co
     by_mag(lattice::Fluid<27>{});
   }
   return 0;
+}
+
+// Launch policy of the library (host logic): whether the node-local step may address the
+// arrays of an nx x ny x nz grid of this storage through buffer resources (arith: the launch
+// also reads forcing or writes a saved state), and the threads per row block it launches for a
+// row of nx nodes with FLAME_ROW_THREADS = row_tx (0: unset).
+int hc_buffer_ok(int nx, int ny, int nz, int storage, int arith) {
+  flame_params p{};
+  p.nx = nx;
+  p.ny = ny;
+  p.nz = nz;
+  p.storage = storage;
+  return buffer_addressing_ok(p, arith != 0) ? 1 : 0;
+}
+unsigned hc_row_threads(int nx, int row_tx) {
+  flame_ctx c;
+  c.p.nx = nx;
+  c.row_tx = row_tx;
+  return row_threads(&c);
 }
 
 }  // extern "C"

@@ -34,6 +34,9 @@ def hc(tmp_path_factory):
     lib.hc_init.argtypes = [D] * 7 + [I, D, D]
     lib.hc_init_vjp.argtypes = [D] * 6 + [I] + [D] * 6
     lib.hc_variant_collide.argtypes = [ctypes.c_int] * 4 + [D] * 7
+    lib.hc_buffer_ok.argtypes = [ctypes.c_int] * 5
+    lib.hc_row_threads.argtypes = [ctypes.c_int] * 2
+    lib.hc_row_threads.restype = ctypes.c_uint
     return lib
 
 
@@ -203,3 +206,29 @@ def test_variant_collision_matches_oracle(hc, fl, ml, coll, mag):
         df = fo + rest.f.reshape(-1).numpy() - want.f.reshape(-1).numpy()
         dg = go + rest.g.reshape(-1).numpy() - want.g.reshape(-1).numpy()
         assert np.abs(df).max() < 1e-15 and np.abs(dg).max() < 1e-15, (trial, np.abs(df).max(), np.abs(dg).max())
+
+
+def test_launch_policy(hc):
+    """Host logic of the launches: buffer resources only where every array the step touches ends
+    at least 16 bytes below 4 GiB (populations of 2^30 FP32 values, exactly 4 GiB, and of 2^29
+    FP64 values take the global addresses; 2^30 FP16 values, 2 GiB, and 512^3 FP64 do not; the
+    [n] arrays of the arithmetic type count only when the launch reads forcing or writes a saved
+    state), and row blocks never beyond the kernels' launch bound of 256 threads, whatever
+    FLAME_ROW_THREADS asks for."""
+    F64, F32, F16 = 0, 1, 2
+    for arith in (0, 1):
+        assert hc.hc_buffer_ok(512, 512, 512, F32, arith) == 1
+        assert hc.hc_buffer_ok(512, 512, 512, F64, arith) == 1
+        assert hc.hc_buffer_ok(1024, 1024, 1024, F32, arith) == 0
+        assert hc.hc_buffer_ok(1024, 1024, 512, F64, arith) == 0      # 2^29 FP64 values: 4 GiB per array
+        assert hc.hc_buffer_ok(1024, 1024, 511, F64, arith) == 1
+    # 2^30 FP16 populations fit (2 GiB); an FP32 forcing or saved-state array of 2^30 values does not
+    assert hc.hc_buffer_ok(1024, 1024, 1024, F16, 0) == 1
+    assert hc.hc_buffer_ok(1024, 1024, 1024, F16, 1) == 0
+    assert hc.hc_buffer_ok(1024, 1024, 1023, F16, 1) == 1
+    assert hc.hc_row_threads(512, 0) == 256
+    assert hc.hc_row_threads(100, 0) == 128
+    assert hc.hc_row_threads(512, 128) == 128
+    assert hc.hc_row_threads(512, 512) == 256
+    assert hc.hc_row_threads(512, 4096) == 256
+    assert hc.hc_row_threads(40, 192) == 64
