@@ -51,6 +51,29 @@ def test_trace_reproduces_steps(jmode, storage, layout):
     assert torch.equal(after, lat[k])          # and reproduce its steps bitwise
 
 
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_trace_reproduces_steps_at_benchmark_size(storage):
+    """The same at the benchmark's size and launch configuration (512^3 forced, moment J, AA):
+    the exported lattice stepped twice with flame_trace_step (a pull step over arrays of stride
+    n, in the node-local kernel with the addressing it takes for this storage) equals the
+    context's own two steps bit for bit."""
+    import bench
+    from paper_2212_11024_amd import _lib as L
+    print(f"[trace] 512^3 {storage}", flush=True)
+    s = bench.make_solver(512, storage, "moment", "aa")
+    s.step(1)
+    nb = L.flame_trace_bytes(s.ctx)
+    lat = torch.empty((3, nb), dtype=torch.uint8, device=s.device)
+    L.flame_trace_export(s.ctx, lat[0].data_ptr())
+    for t in range(2):
+        L.flame_trace_step(s.ctx, lat[t].data_ptr(), lat[t + 1].data_ptr())
+    s.step(2)
+    L.flame_trace_export(s.ctx, lat[0].data_ptr())
+    torch.cuda.synchronize()
+    assert torch.equal(lat[0], lat[2])
+    s.close()
+
+
 def test_trace_argument_errors():
     """Host-side refusals only: no kernel is launched by any trace call below."""
     from paper_2212_11024_amd import _lib as L
