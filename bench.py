@@ -43,12 +43,14 @@ HBM_PEAK_GBPS = 8000.0        # MI355X HBM3E peak
 # a plain copy (see the traffic summary named below). Valid only for the kernel source it was
 # measured on: reported as null once the fingerprint of the kernel sources changes.
 TRAFFIC_RECORDS = {
-    ("f32", "moment"): {"fingerprint": "7a3a1d0178d5c853", "GB_per_launch": 55.3,
+    ("f32", "moment", "aa"): {"fingerprint": "7a3a1d0178d5c853", "GB_per_launch": 55.3,
                         "profile": "profiles/traffic_step_f32_moment_512.md"},
-    ("f32", "stencil"): {"fingerprint": "7a3a1d0178d5c853", "GB_per_launch": 65.4,
+    ("f32", "stencil", "aa"): {"fingerprint": "7a3a1d0178d5c853", "GB_per_launch": 65.4,
                          "profile": "profiles/traffic_step_f32_stencil_512.md"},
-    ("f64", "moment"): {"fingerprint": "7a3a1d0178d5c853", "GB_per_launch": 110.4,
+    ("f64", "moment", "aa"): {"fingerprint": "7a3a1d0178d5c853", "GB_per_launch": 110.4,
                         "profile": "profiles/traffic_step_f64_moment_512.md"},
+    ("f32", "stencil", "ab"): {"fingerprint": "7a3a1d0178d5c853", "GB_per_launch": 66.5,
+                               "profile": "profiles/traffic_step_f32_stencil_ab_512.md"},
 }
 
 
@@ -104,9 +106,9 @@ def bytes_per_node(storage, forced=True, fluid_lattice="d3q27", magnetic_lattice
 
 
 def time_variant(n, storage, jmode, d_i, steps, warmup, fields, collision="central", magnetic="hall",
-                 placement_trials=1, fluid_lattice="d3q27", magnetic_lattice="d3q7"):
+                 placement_trials=1, fluid_lattice="d3q27", magnetic_lattice="d3q7", layout="aa"):
     import torch
-    s = make_solver(n, storage, jmode, "aa", fields=fields, d_i=d_i, collision=collision, magnetic=magnetic,
+    s = make_solver(n, storage, jmode, layout, fields=fields, d_i=d_i, collision=collision, magnetic=magnetic,
                     placement_trials=placement_trials, fluid_lattice=fluid_lattice,
                     magnetic_lattice=magnetic_lattice)
     placement = s.placement_ms
@@ -131,7 +133,7 @@ def time_variant(n, storage, jmode, d_i, steps, warmup, fields, collision="centr
     bpn = bytes_per_node(storage, True, fluid_lattice, magnetic_lattice)
     return {
         "storage": storage, "jmode": jmode, "d_i": d_i, "collision": collision, "magnetic": magnetic,
-        "fluid_lattice": fluid_lattice, "magnetic_lattice": magnetic_lattice,
+        "fluid_lattice": fluid_lattice, "magnetic_lattice": magnetic_lattice, "layout": layout,
         "ms_per_step": ms, "wall_s": wall,
         "mlups": nodes / (ms * 1e-3) / 1e6,
         "bytes_per_node": bpn,
@@ -482,7 +484,7 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--size", type=int, default=512)
     ap.add_argument("--variants", default="all",
-                    choices=["all", "headline", "stencil", "f64", "adjoint", "orszag-tang"],
+                    choices=["all", "headline", "stencil", "stencil-ab", "f64", "adjoint", "orszag-tang"],
                     help="all | headline | stencil (the FP32 stencil kernel alone) | f64 (the FP64 moment-route "
                          "step alone) | adjoint (the reverse-mode "
                          "segments alone, printed as one JSON list) | orszag-tang (the paper's own workload "
@@ -522,13 +524,19 @@ def main(argv=None):
     fields = workload_fields(n, "cuda")
     torch.cuda.synchronize()
     d_i = PHYS["d_i"]
-    single = {"stencil": ("f32", "stencil"), "f64": ("f64", "moment")}.get(args.variants, ("f32", "moment"))
-    variants = [(*single, d_i)]
+    if args.variants == "stencil-ab":
+        variants = [("f32", "stencil", d_i, "central", "hall", "d3q27", "d3q7", "ab")]
+    else:
+        single = {"stencil": ("f32", "stencil"), "f64": ("f64", "moment")}.get(args.variants, ("f32", "moment"))
+        variants = [(*single, d_i)]
     if args.variants == "all":
         # The headline (first entry) is measured last: in a fresh process the first population
         # buffers obtained were all of the slow physical placement in two of three bench runs,
         # while later draws were mostly fast (the trial times are reported for every run).
-        variants = [("f32", "stencil", d_i), ("f32", "stencil", 0.0), ("f64", "moment", d_i),
+        variants = [("f32", "stencil", d_i), ("f32", "stencil", 0.0),
+                    # the stencil kernel with the fluid set in two lattices (AB layout)
+                    ("f32", "stencil", d_i, "central", "hall", "d3q27", "d3q7", "ab"),
+                    ("f64", "moment", d_i),
                     ("f64", "stencil", d_i), ("f16", "moment", d_i), ("f16", "stencil", d_i),
                     # the other two Hall parameters of the forced configuration (MHD to Hall-MHD)
                     ("f32", "moment", 0.0), ("f32", "moment", 16.0),
@@ -540,11 +548,11 @@ def main(argv=None):
                     ("f32", "moment", d_i, "central", "hall", "d3q27", "d3q27")] + variants
     results = []
     for storage, jmode, di, *model in variants:
-        coll, mag, fl, ml = (list(model) + ["central", "hall", "d3q27", "d3q7"][len(model):])
-        print(f"[bench] {n}^3 {storage} {jmode} d_i={di} {coll} {mag} {fl}/{ml}: {args.warmup} warm-up + {args.steps} "
-              "timed steps", file=sys.stderr, flush=True)
+        coll, mag, fl, ml, lay = (list(model) + ["central", "hall", "d3q27", "d3q7", "aa"][len(model):])
+        print(f"[bench] {n}^3 {storage} {jmode} d_i={di} {coll} {mag} {fl}/{ml} {lay}: {args.warmup} warm-up + "
+              f"{args.steps} timed steps", file=sys.stderr, flush=True)
         r = time_variant(n, storage, jmode, di, args.steps, args.warmup, fields, coll, mag, args.placement_trials,
-                         fl, ml)
+                         fl, ml, lay)
         print(f"[bench]   {r['ms_per_step']:.3f} ms/step, {r['mlups']:.0f} MLUPS, {r['achieved_GBps']:.0f} GB/s, "
               f"non-finite nodes {r['nonfinite_nodes']}", file=sys.stderr, flush=True)
         results.append(r)
@@ -580,7 +588,7 @@ def main(argv=None):
     head = results[0]
 
     def traffic_of(r):
-        rec = TRAFFIC_RECORDS.get((r["storage"], r["jmode"]))
+        rec = TRAFFIC_RECORDS.get((r["storage"], r["jmode"], r["layout"]))
         if (n == 512 and rec and (r["collision"], r["magnetic"]) == ("central", "hall") and r["d_i"] == d_i
                 and (r["fluid_lattice"], r["magnetic_lattice"]) == ("d3q27", "d3q7")
                 and kernel_fingerprint() == rec["fingerprint"]):
@@ -628,7 +636,8 @@ def main(argv=None):
                        "FP32", head["storage"].upper().replace("F", "FP")),
                    "grid": [n, n, n], "nu": PHYS["nu"], "eta": PHYS["eta"], "d_i": PHYS["d_i"],
                    "j_mode": head["jmode"],
-                   "layout": "aa (fluid in place; magnetic in place for moment J, two lattices for stencil J)",
+                   "layout": ("aa (fluid in place; magnetic in place for moment J, two lattices for stencil J)"
+                              if head["layout"] == "aa" else "ab (two lattices for both sets, pull streaming)"),
                    "forcing": "static, |k| <= 2, rms 1e-5",
                    "placement": f"fastest of up to {args.placement_trials} population buffers over a 3-step "
                                 "probe each (trial timings in the variants' placement_trials_ms)"},
