@@ -134,7 +134,8 @@ def test_array_size_limit(lib):
     ({"nu": 0.0}, "nu"), ({"eta": -1.0}, "eta"), ({"d_i": -2.0}, "d_i"), ({"shape": (0, 4, 4)}, "grid"),
     ({"shape": (2, 8, 8), "jmode": L.FLAME_J_STENCIL}, "stencil"), ({"storage": 7}, "storage"),
     ({"layout": 9}, "layout"), ({"nu": float("nan")}, "nu"), ({"collision": 2}, "collision"),
-    ({"magnetic": -1}, "magnetic"),
+    ({"magnetic": -1}, "magnetic"), ({"shape": (4, 4, 65536)}, "nz"),
+    ({"shape": (8, 2, 8), "jmode": L.FLAME_J_STENCIL}, "stencil"),
 ])
 def test_invalid_parameters_rejected_before_device_use(lib, kw, msg):
     p = _params(**kw)
