@@ -484,11 +484,12 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--size", type=int, default=512)
     ap.add_argument("--variants", default="all",
-                    choices=["all", "headline", "stencil", "stencil-ab", "f64", "adjoint", "orszag-tang"],
+                    choices=["all", "headline", "stencil", "stencil-ab", "f64", "adjoint", "orszag-tang", "large"],
                     help="all | headline | stencil (the FP32 stencil kernel alone) | f64 (the FP64 moment-route "
                          "step alone) | adjoint (the reverse-mode "
                          "segments alone, printed as one JSON list) | orszag-tang (the paper's own workload "
-                         "alone, FP64 and FP32, one JSON list)")
+                         "alone, FP64 and FP32, one JSON list) | large (the 1024^3 configuration alone, one "
+                         "JSON object)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-copy-probe", action="store_true",
@@ -514,6 +515,9 @@ def main(argv=None):
     adjoint_cases = (("moment", "trace"), ("moment", "state"), ("stencil", "state"))
     if args.variants == "adjoint":
         print(json.dumps([adjoint_timing(128, "f32", jm, recompute=rc) for jm, rc in adjoint_cases]), flush=True)
+        return 0
+    if args.variants == "large":
+        print(json.dumps(large_configuration(placement_trials=args.placement_trials)), flush=True)
         return 0
     if args.variants == "orszag-tang":
         print(json.dumps([orszag_tang_timing(args.size, st, args.steps, args.warmup, args.placement_trials)

@@ -37,6 +37,7 @@ struct View {
   size_t n;
   size_t stride;   // elements between population arrays
 
+  // node index in 32-bit arithmetic: flame_init refuses grids of 2^32 nodes or more
   __device__ size_t node(int x, int y, int z) const {
     return (static_cast<size_t>(z) * ny + y) * nx + x;
   }
@@ -52,6 +53,23 @@ struct View {
                       : static_cast<size_t>((gmode == 1 ? oppm(i) : i) * 3 + c) * stride +
                             node(wrap(x - xim(i, 0), nx), wrap(y - xim(i, 1), ny), wrap(z - xim(i, 2), nz));
   }
+  // the same with the addressing mode fixed at compile time (no branch per access, so that a
+  // node's loads can all be in flight together)
+  template <int M>
+  __device__ double fm(int i, int x, int y, int z) const {
+    const size_t idx = M == 0 ? static_cast<size_t>(i) * stride + node(x, y, z)
+                              : static_cast<size_t>(M == 1 ? oppq(i) : i) * stride +
+                                    node(wrap(x - cq(i, 0), nx), wrap(y - cq(i, 1), ny), wrap(z - cq(i, 2), nz));
+    return static_cast<double>(F[idx]) / Enc<S>::fscale(i);
+  }
+  template <int M>
+  __device__ double gm(int i, int c, int x, int y, int z) const {
+    const size_t idx = M == 0 ? static_cast<size_t>(i * 3 + c) * stride + node(x, y, z)
+                              : static_cast<size_t>((M == 1 ? oppm(i) : i) * 3 + c) * stride +
+                                    node(wrap(x - xim(i, 0), nx), wrap(y - xim(i, 1), ny), wrap(z - xim(i, 2), nz));
+    return static_cast<double>(G[idx]) / Enc<S>::mscale(i);
+  }
+  // runtime mode: the element index is selected, then one load
   __device__ double f(int i, int x, int y, int z) const {
     size_t idx = fmode == 0 ? static_cast<size_t>(i) * stride + node(x, y, z)
                             : static_cast<size_t>(fmode == 1 ? oppq(i) : i) * stride +
@@ -65,6 +83,30 @@ struct View {
     return static_cast<double>(G[idx]) / Enc<S>::mscale(i);
   }
 };
+
+// All populations of node (x, y, z), decoded, in canonical order; the mode switch is taken once
+// per node.
+template <int M, typename S>
+__device__ __forceinline__ void view_fluid(const View<S>& v, int x, int y, int z, double (&f)[kQ]) {
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) f[i] = v.template fm<M>(i, x, y, z);
+}
+template <int M, typename S>
+__device__ __forceinline__ void view_magnetic(const View<S>& v, int x, int y, int z, double (&g)[kM]) {
+#pragma unroll
+  for (int i = 0; i < 7; ++i)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) g[i * 3 + c] = v.template gm<M>(i, c, x, y, z);
+}
+template <typename S>
+__device__ __forceinline__ void view_node(const View<S>& v, int x, int y, int z, double (&f)[kQ], double (&g)[kM]) {
+  if (v.fmode == 0) view_fluid<0>(v, x, y, z, f);
+  else if (v.fmode == 1) view_fluid<1>(v, x, y, z, f);
+  else view_fluid<2>(v, x, y, z, f);
+  if (v.gmode == 0) view_magnetic<0>(v, x, y, z, g);
+  else if (v.gmode == 1) view_magnetic<1>(v, x, y, z, g);
+  else view_magnetic<2>(v, x, y, z, g);
+}
 
 // Where a writer of the canonical state (initial state, set) puts population i of node
 // (x, y, z): its own slot for in-place sets; for pull sets the slot at x - c_i, which is where
@@ -106,27 +148,49 @@ __device__ double field_fluct(const AuxArgs<S>& a, int comp, int x, int y, int z
   if (a.force_b) s += 0.5 * static_cast<double>(a.force_b[static_cast<size_t>(comp) * a.v.n + a.v.node(x, y, z)]);
   return s;
 }
+// the same with the magnetic addressing mode fixed at compile time (same order of the sum)
+template <int M, typename S>
+__device__ __forceinline__ double field_fluct_m(const AuxArgs<S>& a, int comp, int x, int y, int z) {
+  double s = a.v.template gm<M>(0, comp, x, y, z);
+#pragma unroll
+  for (int i = 1; i < 7; ++i) s += a.v.template gm<M>(i, comp, x, y, z);
+  if (a.force_b) s += 0.5 * static_cast<double>(a.force_b[static_cast<size_t>(comp) * a.v.n + a.v.node(x, y, z)]);
+  return s;
+}
+// J = central-difference curl of b at node (x, y, z)
+template <int M, typename S>
+__device__ __forceinline__ void curl_b(const AuxArgs<S>& a, int x, int y, int z, double (&J)[3]) {
+  const View<S>& v = a.v;
+  const int xp = wrap(x + 1, v.nx), xm = wrap(x - 1, v.nx);
+  const int yp = wrap(y + 1, v.ny), ym = wrap(y - 1, v.ny);
+  const int zp = wrap(z + 1, v.nz), zm = wrap(z - 1, v.nz);
+  J[0] = 0.5 * (field_fluct_m<M>(a, 2, x, yp, z) - field_fluct_m<M>(a, 2, x, ym, z))
+       - 0.5 * (field_fluct_m<M>(a, 1, x, y, zp) - field_fluct_m<M>(a, 1, x, y, zm));
+  J[1] = 0.5 * (field_fluct_m<M>(a, 0, x, y, zp) - field_fluct_m<M>(a, 0, x, y, zm))
+       - 0.5 * (field_fluct_m<M>(a, 2, xp, y, z) - field_fluct_m<M>(a, 2, xm, y, z));
+  J[2] = 0.5 * (field_fluct_m<M>(a, 1, xp, y, z) - field_fluct_m<M>(a, 1, xm, y, z))
+       - 0.5 * (field_fluct_m<M>(a, 0, x, yp, z) - field_fluct_m<M>(a, 0, x, ym, z));
+}
 
 template <typename S>
 __device__ NodeQ node_quantities(const AuxArgs<S>& a, int x, int y, int z) {
   NodeQ q;
   const View<S>& v = a.v;
   const size_t cell = v.node(x, y, z);
+  // unrolled, so that f and g stay in registers (a runtime index would put them in scratch)
   double f[kQ], g[kM];
+  view_node(v, x, y, z, f, g);
   bool fin = true;
-  for (int i = 0; i < kQ; ++i) {
-    f[i] = v.f(i, x, y, z);
-    fin = fin && isfinite(f[i]);
-  }
-  for (int i = 0; i < 7; ++i)
-    for (int c = 0; c < 3; ++c) {
-      g[i * 3 + c] = v.g(i, c, x, y, z);
-      fin = fin && isfinite(g[i * 3 + c]);
-    }
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) fin = fin && isfinite(f[i]);
+#pragma unroll
+  for (int q = 0; q < kM; ++q) fin = fin && isfinite(g[q]);
   q.finite = fin;
   double drho = 0, j[3] = {0, 0, 0};
+#pragma unroll
   for (int i = 0; i < kQ; ++i) {
     drho += f[i];
+#pragma unroll
     for (int c = 0; c < 3; ++c) j[c] += cq(i, c) * f[i];
   }
   q.rho = 1.0 + drho;
@@ -145,21 +209,18 @@ __device__ NodeQ node_quantities(const AuxArgs<S>& a, int x, int y, int z) {
   if (!a.stencil) {
     const double zero[3] = {0.0, 0.0, 0.0};
     current_from_moments(lam, a.emhd ? zero : q.U, q.B, a.alpha, a.omega_b, q.J);
+  } else if (v.gmode == 0) {
+    curl_b<0>(a, x, y, z, q.J);
+  } else if (v.gmode == 1) {
+    curl_b<1>(a, x, y, z, q.J);
   } else {
-    const int xp = wrap(x + 1, v.nx), xm = wrap(x - 1, v.nx);
-    const int yp = wrap(y + 1, v.ny), ym = wrap(y - 1, v.ny);
-    const int zp = wrap(z + 1, v.nz), zm = wrap(z - 1, v.nz);
-    q.J[0] = 0.5 * (field_fluct(a, 2, x, yp, z) - field_fluct(a, 2, x, ym, z))
-           - 0.5 * (field_fluct(a, 1, x, y, zp) - field_fluct(a, 1, x, y, zm));
-    q.J[1] = 0.5 * (field_fluct(a, 0, x, y, zp) - field_fluct(a, 0, x, y, zm))
-           - 0.5 * (field_fluct(a, 2, xp, y, z) - field_fluct(a, 2, xm, y, z));
-    q.J[2] = 0.5 * (field_fluct(a, 1, xp, y, z) - field_fluct(a, 1, xm, y, z))
-           - 0.5 * (field_fluct(a, 0, x, yp, z) - field_fluct(a, 0, x, ym, z));
+    curl_b<2>(a, x, y, z, q.J);
   }
   q.divb = -4.0 * a.omega_b * (lam[0][0] + lam[1][1] + lam[2][2]);
   return q;
 }
 
+// cell < 2^32 (flame_init refuses larger grids), so 32-bit division suffices
 __device__ __forceinline__ void node_xyz(size_t cell, int nx, int ny, int& x, int& y, int& z) {
   x = static_cast<int>(cell % nx);
   const size_t r = cell / nx;
@@ -382,7 +443,7 @@ constexpr int kRedBlocksMax = 2048;
 // Per-block partials: sums in every slot except 4 and 6 (maxima). Fixed grid and a fixed
 // tree order make the result bitwise reproducible.
 template <typename S>
-__global__ __launch_bounds__(kRedThreads) void reduce_kernel(AuxArgs<S> a, double* partials) {
+__global__ __launch_bounds__(kRedThreads, 2) void reduce_kernel(AuxArgs<S> a, double* partials) {
   double acc[FLAME_NRED];
   for (int k = 0; k < FLAME_NRED; ++k) acc[k] = 0.0;
   const size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
