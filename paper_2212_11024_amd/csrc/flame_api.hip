@@ -184,7 +184,7 @@ __device__ NodeQ node_quantities(const AuxArgs<S>& a, int x, int y, int z) {
 #pragma unroll
   for (int i = 0; i < kQ; ++i) fin = fin && isfinite(f[i]);
 #pragma unroll
-  for (int q = 0; q < kM; ++q) fin = fin && isfinite(g[q]);
+  for (int k = 0; k < kM; ++k) fin = fin && isfinite(g[k]);
   q.finite = fin;
   double drho = 0, j[3] = {0, 0, 0};
 #pragma unroll
