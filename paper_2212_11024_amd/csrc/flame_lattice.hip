@@ -152,16 +152,21 @@ template <typename S, typename FL, typename ML>
 __device__ void node_q(const VAux<S, FL, ML>& a, int x, int y, int z, double& rho, double (&U)[3], double (&B)[3],
                        double (&b)[3], double (&J)[3], double& divb, bool& finite) {
   const size_t cell = vnode(x, y, z, a.v.geo.nx, a.v.geo.ny);
+  // unrolled, so that g stays in registers (a runtime index would put it in scratch)
   double g[ML::m * 3];
   bool fin = true;
   double drho = 0, j[3] = {0, 0, 0};
+#pragma unroll
   for (int i = 0; i < FL::q; ++i) {
     const double fi = a.v.f(i, x, y, z);
     fin = fin && isfinite(fi);
     drho += fi;
+#pragma unroll
     for (int c = 0; c < 3; ++c) j[c] += FL::c(i, c) * fi;
   }
+#pragma unroll
   for (int i = 0; i < ML::m; ++i)
+#pragma unroll
     for (int c = 0; c < 3; ++c) {
       g[i * 3 + c] = a.v.g(i, c, x, y, z);
       fin = fin && isfinite(g[i * 3 + c]);
@@ -417,7 +422,10 @@ __global__ __launch_bounds__(256) void variant_component(VAux<S, FL, ML> a, int 
   double r, U[3], Bf[3], b[3], Jf[3], d;
   bool fin;
   node_q(a, x, y, z, r, U, Bf, b, Jf, d, fin);
-  out[cell] = field == 0 ? U[comp] : Bf[comp];
+  // selected without a runtime index into the arrays (which would put them in scratch)
+  const double uc = comp == 0 ? U[0] : comp == 1 ? U[1] : U[2];
+  const double bc = comp == 0 ? Bf[0] : comp == 1 ? Bf[1] : Bf[2];
+  out[cell] = field == 0 ? uc : bc;
 }
 
 // Block partials of the FP64 reductions in the slot order of flame_reduce (fixed grid, fixed
