@@ -177,7 +177,7 @@ __device__ NodeQ node_quantities(const AuxArgs<S>& a, int x, int y, int z) {
   NodeQ q;
   const View<S>& v = a.v;
   const size_t cell = v.node(x, y, z);
-  // unrolled, so that f and g stay in registers (a runtime index would put them in scratch)
+  // unrolled, so that f and g stay in registers (a runtime index would put them in per-thread private memory)
   double f[kQ], g[kM];
   view_node(v, x, y, z, f, g);
   bool fin = true;

@@ -152,7 +152,7 @@ template <typename S, typename FL, typename ML>
 __device__ void node_q(const VAux<S, FL, ML>& a, int x, int y, int z, double& rho, double (&U)[3], double (&B)[3],
                        double (&b)[3], double (&J)[3], double& divb, bool& finite) {
   const size_t cell = vnode(x, y, z, a.v.geo.nx, a.v.geo.ny);
-  // unrolled, so that g stays in registers (a runtime index would put it in scratch)
+  // unrolled, so that g stays in registers (a runtime index would put it in per-thread private memory)
   double g[ML::m * 3];
   bool fin = true;
   double drho = 0, j[3] = {0, 0, 0};
@@ -422,7 +422,7 @@ __global__ __launch_bounds__(256) void variant_component(VAux<S, FL, ML> a, int 
   double r, U[3], Bf[3], b[3], Jf[3], d;
   bool fin;
   node_q(a, x, y, z, r, U, Bf, b, Jf, d, fin);
-  // selected without a runtime index into the arrays (which would put them in scratch)
+  // selected without a runtime index into the arrays (which would put them in per-thread private memory)
   const double uc = comp == 0 ? U[0] : comp == 1 ? U[1] : U[2];
   const double bc = comp == 0 ? Bf[0] : comp == 1 ? Bf[1] : Bf[2];
   out[cell] = field == 0 ? uc : bc;
