@@ -441,7 +441,9 @@ constexpr int kRedThreads = 256;
 constexpr int kRedBlocksMax = 2048;
 
 // Per-block partials: sums in every slot except 4 and 6 (maxima). Fixed grid and a fixed
-// tree order make the result bitwise reproducible.
+// tree order make the result bitwise reproducible. Two blocks per CU at least: without that
+// bound the FP64 instantiation takes 261 VGPRs (one wave per SIMD) and runs slower than with
+// the few spills the bound costs.
 template <typename S>
 __global__ __launch_bounds__(kRedThreads, 2) void reduce_kernel(AuxArgs<S> a, double* partials) {
   double acc[FLAME_NRED];
