@@ -44,3 +44,13 @@ def test_reductions_and_node_fields_keep_the_node_in_registers(tmp_path):
             assert priv <= 64 and vgpr <= 256, (k, priv, vgpr)
         else:
             assert priv == 0, (k, priv)
+
+
+@pytest.mark.skipif(shutil.which("hipcc") is None and not os.path.exists("/opt/rocm/bin/hipcc"),
+                    reason="hipcc is not installed")
+def test_lattice_variant_node_fields_keep_the_node_in_registers(tmp_path):
+    meta = _kernel_metadata("flame_lattice.hip", tmp_path)
+    checked = [k for k in meta if "variant_moments" in k or "variant_component" in k or "variant_reduce" in k]
+    assert len(checked) >= 18, checked
+    for k in checked:
+        assert meta[k][0] == 0, (k, meta[k])
